@@ -1,0 +1,193 @@
+"""ctypes shim over the serial FP64 oracle (``emma_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, by the smoke check and
+by the benchmark's CPU-baseline leg, never by the library under
+``paper_1508_07888_amd``.  It marshals numpy arrays and holds none of the
+method's arithmetic.
+
+Layouts (C order, x fastest): N[G,nz,ny,nx], F[G,3,nz,ny,nx], x/T/n0[nz,ny,nx].
+Units CGS.  ``groups`` is the dict {"sigma_N", "sigma_E", "mean_E", "frac"}
+of per-group constants (cm^2, cm^2, erg, dimensionless).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+COUNTER_NAMES = ("limiter", "neg_clamp", "x_clamp", "cap_hits",
+                 "substeps", "attempts", "max_sub")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.oracle_run.restype = ctypes.c_int
+        L.oracle_run.argtypes = [_ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                 _lp, _dp, ctypes.c_int, _lp, _lp]
+        L.oracle_run_tangent.restype = ctypes.c_int
+        L.oracle_run_tangent.argtypes = [_ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                         _lp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp,
+                                         _lp]
+        L.oracle_transport.restype = ctypes.c_int
+        L.oracle_transport.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _lp]
+        L.oracle_chem_cell.restype = ctypes.c_int
+        L.oracle_chem_cell.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double,
+                                       _dp, _lp]
+        L.oracle_pressure.restype = None
+        L.oracle_pressure.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp]
+        L.oracle_face_flux.restype = None
+        L.oracle_face_flux.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp,
+                                       ctypes.c_int, ctypes.c_double, _dp]
+        L.oracle_rates.restype = None
+        L.oracle_rates.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int, _dp]
+        L.oracle_cross_section.restype = ctypes.c_double
+        L.oracle_cross_section.argtypes = [ctypes.c_double]
+        L.oracle_group_constants.restype = None
+        L.oracle_group_constants.argtypes = [ctypes.c_double, _dp, ctypes.c_int, ctypes.c_int,
+                                             _dp, _dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _pack(shape, G, dx, c_red, dt, groups, otsa=1, isothermal=0, max_substeps=100000):
+    nz, ny, nx = shape
+    ints = np.array([nx, ny, nz, G, otsa, isothermal, max_substeps], dtype=np.int32)
+    dbls = np.array([dx, c_red, dt], dtype=np.float64)
+    gr = np.zeros((4, 4), dtype=np.float64)
+    for r, key in enumerate(("sigma_N", "sigma_E", "mean_E", "frac")):
+        v = np.asarray(groups[key], dtype=np.float64)
+        gr[r, :G] = v[:G]
+    return ints, dbls, gr
+
+
+def _counters(c):
+    return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
+
+
+def run(N, F, x, T, n0, src_cell, src_rate, *, dx, c_red, dt, n_steps, groups,
+        otsa=1, isothermal=0, max_substeps=100000, return_substeps=False):
+    """Advance (N, F, x, T) by ``n_steps`` steps of ``dt``; returns copies and
+    the counter dict (and per-cell accepted-substep totals if asked)."""
+    N = _f64(N).copy(); F = _f64(F).copy(); x = _f64(x).copy(); T = _f64(T).copy()
+    n0 = _f64(n0)
+    G = N.shape[0]
+    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps)
+    sc = np.ascontiguousarray(src_cell, dtype=np.int64)
+    sr = _f64(src_rate)
+    sub = np.zeros(n0.size, dtype=np.int64)
+    cnt = np.zeros(7, dtype=np.int64)
+    rc = lib().oracle_run(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), int(n_steps),
+                          _d(N), _d(F), _d(x), _d(T), _d(n0),
+                          sc.ctypes.data_as(_lp), _d(sr), int(sc.size),
+                          sub.ctypes.data_as(_lp), cnt.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError("oracle_run rejected its arguments")
+    out = (N, F, x, T, _counters(cnt))
+    if return_substeps:
+        out = out + (sub.reshape(n0.shape),)
+    return out
+
+
+def run_tangent(N, F, x, T, n0, src_cell, src_rate, dN, dF, dxh, dT, dn0, drate, *,
+                dx, c_red, dt, n_steps, groups, otsa=1, isothermal=0, max_substeps=100000):
+    """Forward run carried in dual numbers: returns the end state, its
+    directional derivative along (dN, dF, dxh, dT, dn0, drate), and counters."""
+    N = _f64(N).copy(); F = _f64(F).copy(); x = _f64(x).copy(); T = _f64(T).copy()
+    dN = _f64(dN).copy(); dF = _f64(dF).copy(); dxh = _f64(dxh).copy(); dT = _f64(dT).copy()
+    n0 = _f64(n0); dn0 = _f64(dn0)
+    sc = np.ascontiguousarray(src_cell, dtype=np.int64)
+    sr = _f64(src_rate); dr = _f64(drate)
+    G = N.shape[0]
+    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps)
+    cnt = np.zeros(7, dtype=np.int64)
+    rc = lib().oracle_run_tangent(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), int(n_steps),
+                                  _d(N), _d(F), _d(x), _d(T), _d(n0),
+                                  sc.ctypes.data_as(_lp), _d(sr), int(sc.size),
+                                  _d(dN), _d(dF), _d(dxh), _d(dT), _d(dn0), _d(dr),
+                                  cnt.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError("oracle_run_tangent rejected its arguments")
+    return (N, F, x, T), (dN, dF, dxh, dT), _counters(cnt)
+
+
+def transport(N, F, *, dx, c_red, dt):
+    """One conservative transport update (no chemistry) of every group."""
+    N = _f64(N); F = _f64(F)
+    G = N.shape[0]
+    dummy = {"sigma_N": [0] * 4, "sigma_E": [0] * 4, "mean_E": [0] * 4, "frac": [0] * 4}
+    ints, dbls, gr = _pack(N.shape[1:], G, dx, c_red, dt, dummy)
+    Ns = np.empty_like(N); Fs = np.empty_like(F)
+    cnt = np.zeros(7, dtype=np.int64)
+    rc = lib().oracle_transport(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), _d(N), _d(F),
+                                _d(Ns), _d(Fs), cnt.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError("oracle_transport rejected its arguments")
+    return Ns, Fs, _counters(cnt)
+
+
+def chem_cell(N, F, x, T, n0, S, *, dt, c_red, groups, otsa=1, isothermal=0,
+              max_substeps=100000, dx=1.0):
+    """Chemistry of one cell: N[G], F[G,3], scalars x, T, n0 and S[G]."""
+    N = _f64(N).copy(); F = _f64(F).copy(); S = _f64(S)
+    G = N.shape[0]
+    ints, dbls, gr = _pack((1, 1, 1), G, dx, c_red, dt, groups, otsa, isothermal, max_substeps)
+    xa = np.array([x], dtype=np.float64); Ta = np.array([T], dtype=np.float64)
+    cnt = np.zeros(7, dtype=np.int64)
+    rc = lib().oracle_chem_cell(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), _d(N), _d(F),
+                                _d(xa), _d(Ta), float(n0), _d(S), cnt.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError("oracle_chem_cell rejected its arguments")
+    return N, F, float(xa[0]), float(Ta[0]), _counters(cnt)
+
+
+def pressure(N, F, c):
+    F = _f64(F); P = np.empty(9, dtype=np.float64)
+    lib().oracle_pressure(float(N), _d(F), float(c), _d(P))
+    return P.reshape(3, 3)
+
+
+def face_flux(NL, FL, NR, FR, d, c):
+    FL = _f64(FL); FR = _f64(FR); out = np.empty(4, dtype=np.float64)
+    lib().oracle_face_flux(float(NL), _d(FL), float(NR), _d(FR), int(d), float(c), _d(out))
+    return out
+
+
+def rates(T, n0=1.0, x=0.5, otsa=1):
+    out = np.empty(4, dtype=np.float64)
+    lib().oracle_rates(float(T), float(n0), float(x), int(otsa), _d(out))
+    return {"alpha_A": out[0], "alpha_B": out[1], "beta": out[2], "Lambda": out[3]}
+
+
+def cross_section(E_eV):
+    return lib().oracle_cross_section(float(E_eV))
+
+
+def group_constants(T_bb, edges_eV, panels=20000):
+    e = _f64(edges_eV)
+    G = e.size - 1
+    sN = np.empty(G); sE = np.empty(G); mE = np.empty(G); fr = np.empty(G)
+    lib().oracle_group_constants(float(T_bb), _d(e), G, int(panels), _d(sN), _d(sE), _d(mE),
+                                 _d(fr))
+    return {"sigma_N": sN, "sigma_E": sE, "mean_E": mE, "frac": fr}

@@ -1,0 +1,454 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formula: each checks a closed form,
+an invariant, a special case that reduces to a textbook result, or an exact
+property of the discrete scheme.  Citations are to sections and equations of
+Aubert, Deparis & Ocvirk (2015).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import emma_inputs as E
+import oracle
+
+C = E.C_LIGHT
+KB = 1.380649e-16
+EV = 1.602176634e-12
+
+
+def _groups(G=1):
+    return oracle.group_constants(E.T_BB, E.EDGES[G])
+
+
+def _zero_groups(G=1):
+    z = np.zeros(G)
+    return {"sigma_N": z, "sigma_E": z, "mean_E": z, "frac": np.full(G, 1.0 / G)}
+
+
+# --------------------------------------------------------------- M1 closure
+# Sec. 2.2.3: P = D N, chi in [1/3, 1] from the diffusive to the free-streaming limit.
+
+def test_closure_limits():
+    N = 2.5
+    P0 = oracle.pressure(N, [0.0, 0.0, 0.0], C)
+    assert np.allclose(P0, N / 3.0 * np.eye(3), rtol=1e-15, atol=0)
+    n = np.array([1.0, 2.0, -2.0]) / 3.0
+    P1 = oracle.pressure(N, C * N * n, C)
+    assert np.allclose(P1, N * np.outer(n, n), rtol=1e-14, atol=1e-15 * N)
+
+
+def test_closure_trace_psd_symmetric():
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        N = 10 ** rng.uniform(-5, 5)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        f = rng.uniform(0, 1)
+        P = oracle.pressure(N, f * C * N * d, C)
+        assert abs(np.trace(P) - N) <= 1e-14 * N          # tr D = 1
+        assert np.allclose(P, P.T, rtol=0, atol=1e-15 * N)
+        assert np.linalg.eigvalsh(P).min() >= -1e-14 * N
+
+
+def test_closure_boosted_isotropic_radiation():
+    # Levermore's closure is exact for radiation isotropic in a frame moving
+    # with speed b along n: then f = 4b/(3+b^2) and the Eddington factor along
+    # n is (1+3b^2)/(3+b^2), with (1-chi)/2 across n (so tr D = 1).
+    for b in (0.05, 0.2, 0.5, 0.8, 0.95):
+        f = 4 * b / (3 + b * b)
+        chi = (1 + 3 * b * b) / (3 + b * b)
+        n = np.array([0.6, 0.0, 0.8])
+        P = oracle.pressure(1.0, f * C * n, C)
+        assert abs(n @ P @ n - chi) < 1e-14
+        t = np.array([0.8, 0.0, -0.6])
+        assert abs(t @ P @ t - (1 - chi) / 2) < 1e-14
+
+
+def test_closure_f_clipped_and_zero_density():
+    # f > 1 is read as f = 1; N = 0 carries no pressure whatever F says.
+    P = oracle.pressure(1.0, [3.0 * C, 0, 0], C)
+    assert np.allclose(P, np.diag([1.0, 0, 0]), atol=1e-15)
+    assert np.all(oracle.pressure(0.0, [1.0, 2.0, 3.0], C) == 0.0)
+
+
+# ------------------------------------------------------- face flux, eq. e:glf
+
+def test_glf_equals_hll_with_light_speed_signals():
+    # HLL with signal speeds -c and +c: (c F_L + c F_R - c^2 (U_R - U_L)) / (2c).
+    rng = np.random.default_rng(2)
+    for _ in range(100):
+        NL, NR = 10 ** rng.uniform(-3, 1, 2)
+        FL = rng.uniform(-0.5, 0.5, 3) * C * NL
+        FR = rng.uniform(-0.5, 0.5, 3) * C * NR
+        d = int(rng.integers(0, 3))
+        PL, PR = oracle.pressure(NL, FL, C), oracle.pressure(NR, FR, C)
+        UL = np.r_[NL, FL]
+        UR = np.r_[NR, FR]
+        FtL = np.r_[FL[d], C * C * PL[:, d]]
+        FtR = np.r_[FR[d], C * C * PR[:, d]]
+        lm, lp = -C, C
+        hll = (lp * FtL - lm * FtR + lp * lm * (UR - UL)) / (lp - lm)
+        got = oracle.face_flux(NL, FL, NR, FR, d, C)
+        scale = np.r_[C * max(NL, NR), C * C * max(NL, NR) * np.ones(3)]
+        assert np.all(np.abs(got - hll) <= 1e-14 * scale)
+
+
+# ----------------------------------------------------- transport invariants
+
+def _beam_state(n, c, nu, steps, G=1):
+    shape = (4, 3, n)
+    N = np.zeros((G,) + shape)
+    N[:, :, :, 5] = 1.0
+    N[:, :, :, 6] = 0.5
+    F = np.zeros((G, 3) + shape)
+    F[:, 0] = c * N
+    return N, F
+
+
+def test_free_streaming_beam_is_exact_upwind():
+    # A plane beam at f = 1 along x: the flux of eq. (e:glf) reduces to first-order
+    # upwinding for N and F, so the profile after n steps is the binomial
+    # convolution and the front moves at c_red exactly (nu cells per step).
+    nx, nu, steps = 48, 0.8 / 3.0, 30
+    c = 0.1 * C
+    dx = 1e20
+    dt = nu * dx / c
+    N, F = _beam_state(nx, c, nu, steps)
+    for _ in range(steps):
+        N, F, cnt = oracle.transport(N, F, dx=dx, c_red=c, dt=dt)
+        assert cnt["neg_clamp"] == 0
+    N0 = np.zeros(nx)
+    N0[5], N0[6] = 1.0, 0.5
+    expect = np.zeros(nx)
+    for k in range(steps + 1):
+        w = math.comb(steps, k) * nu ** k * (1 - nu) ** (steps - k)
+        expect += w * np.roll(N0, k)
+    got = N[0, 0, 0]
+    assert np.max(np.abs(got - expect)) < 1e-14
+    assert np.allclose(N[0], got[None, None, :], rtol=0, atol=1e-15)
+    assert np.max(np.abs(F[0, 0] - c * N[0])) < 1e-14 * c
+    # centroid of the pulse moved by n nu cells
+    xs = np.arange(nx)
+    c0 = (xs * N0).sum() / N0.sum()
+    c1 = (xs * got).sum() / got.sum()
+    assert abs((c1 - c0) - steps * nu) < 1e-12
+
+
+def test_diffusive_limit_fourier_mode():
+    # Small sinusoidal perturbation of uniform N with F = 0: to first order the
+    # scheme acts on each Fourier mode (N^, F^/c) through
+    #   G(th) = [[1 - nu (1 - cos th), -i nu sin th], [-i nu/3 sin th, 1 - nu (1 - cos th)]],
+    # i.e. the M1 system at f -> 0 (P = N/3) with the Lax-Friedrichs dissipation.
+    nx, nu, steps, eps = 32, 0.25, 12, 1e-7
+    k = 3
+    th = 2 * math.pi * k / nx
+    dx = 1e20
+    c = 0.1 * C
+    dt = nu * dx / c
+    xs = np.arange(nx)
+    N = np.ones((1, 2, 2, nx)) * (1.0 + eps * np.cos(th * xs))
+    F = np.zeros((1, 3, 2, 2, nx))
+    for _ in range(steps):
+        N, F, _ = oracle.transport(N, F, dx=dx, c_red=c, dt=dt)
+    a = 1 - nu * (1 - math.cos(th))
+    s = nu * math.sin(th)
+    Gm = np.array([[a, -1j * s], [-1j * s / 3, a]])
+    v = np.linalg.matrix_power(Gm, steps) @ np.array([eps, 0.0])
+    expect_N = 1.0 + np.real(v[0] * np.exp(1j * th * xs))
+    expect_F = c * np.real(v[1] * np.exp(1j * th * xs))
+    assert np.max(np.abs(N[0, 0, 0] - expect_N)) < 10 * eps * eps + 1e-15
+    assert np.max(np.abs(F[0, 0, 0, 0] - expect_F)) < c * (10 * eps * eps + 1e-15)
+
+
+def test_positivity_and_realisability_at_courant_third():
+    # At c dt/dx <= 1/3 the unsplit update is a convex combination of
+    # realisable states: N* >= 0 and |F*| <= c N* with no clamp needed.
+    c = 0.1 * C
+    dx = 1e20
+    N, F, *_ = E.random_state((10, 9, 8), 2, c, seed=3)
+    dt = E.courant_dt(dx, c)
+    for _ in range(5):
+        N, F, cnt = oracle.transport(N, F, dx=dx, c_red=c, dt=dt)
+        assert cnt["neg_clamp"] == 0
+        assert N.min() >= 0
+        Fn = np.linalg.norm(F, axis=1)
+        assert np.all(Fn <= c * N * (1 + 1e-12) + 1e-300)
+
+
+def test_courant_one_is_not_enough_in_3d():
+    # The printed 1D condition c dt <= dx does not make the unsplit 3D update
+    # positive: at nu = 0.8 a point pulse drives N negative.
+    c = C
+    dx = 1e20
+    N = np.zeros((1, 9, 9, 9))
+    N[0, 4, 4, 4] = 1.0
+    F = np.zeros((1, 3, 9, 9, 9))
+    Ns, Fs, cnt = oracle.transport(N, F, dx=dx, c_red=c, dt=0.8 * dx / c)
+    assert cnt["neg_clamp"] > 0
+
+
+def test_photon_conservation_without_absorber():
+    # No absorber (sigma = 0): the fluxes telescope on the periodic grid and the
+    # sources add rate * frac * dt per step (Sec. 2.2.3-2.2.4).
+    w = E.make_workload("lognormal128", n=12)
+    g = _groups(3)
+    g = dict(g, sigma_N=np.zeros(3), sigma_E=np.zeros(3))
+    steps = 6
+    N, F, x, T, cnt = oracle.run(w["N"], w["F"], w["x"], w["T"], w["n0"], w["src_cell"],
+                                 w["src_rate"], dx=w["dx"], c_red=w["c_red"], dt=w["dt"],
+                                 n_steps=steps, groups=g)
+    vol = w["dx"] ** 3
+    tot = N.reshape(3, -1).sum(axis=1) * vol
+    expect = steps * w["dt"] * w["src_rate"].sum() * g["frac"]
+    assert np.allclose(tot, expect, rtol=1e-13, atol=0)
+    assert cnt["limiter"] == 0 and cnt["neg_clamp"] == 0
+
+
+def test_cube_symmetry_of_centred_source():
+    # A source at the centre of an odd periodic grid with uniform gas: the
+    # solution is invariant under the 48 symmetries of the cube (N as a scalar,
+    # F as a vector).
+    n = 9
+    w = E.make_workload("lognormal128", n=n)
+    g = _groups(2)
+    N, F, x, T = E.initial_state((n, n, n), 2)
+    n0 = np.full((n, n, n), 1e-3)
+    cell = np.array([(4 * n + 4) * n + 4])
+    N, F, x, T, _ = oracle.run(N, F, x, T, n0, cell, np.array([1e50]), dx=w["dx"],
+                               c_red=w["c_red"], dt=w["dt"], n_steps=6, groups=g)
+    import itertools
+    Nmax = N.max()
+    Fmax = np.abs(F).max()
+    z, y, xx = np.indices((n, n, n))
+    r = np.stack([xx - 4, y - 4, z - 4])            # vector components (x, y, z)
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product((1, -1), repeat=3):
+            # M v: component k of the image is flips[k] * v[perm[k]]
+            rp = np.stack([flips[k] * r[perm[k]] for k in range(3)]) + 4
+            sel = (rp[2], rp[1], rp[0])               # (z', y', x') of M r
+            N_Mr = N[(slice(None),) + sel]
+            assert np.max(np.abs(N_Mr - N)) <= 1e-14 * Nmax
+            F_Mr = F[(slice(None), slice(None)) + sel]
+            MF = np.stack([flips[k] * F[:, perm[k]] for k in range(3)], axis=1)
+            assert np.max(np.abs(F_Mr - MF)) <= 1e-14 * Fmax
+            assert np.max(np.abs(x[sel] - x)) <= 1e-14
+
+
+# ------------------------------------------------------------ thermochemistry
+
+def test_rate_anchors():
+    r = oracle.rates(1e4)
+    assert abs(r["alpha_B"] / 2.59e-13 - 1) < 0.005      # case B at 1e4 K (textbook)
+    assert abs(r["alpha_A"] / 4.18e-13 - 1) < 0.04       # case A at 1e4 K (textbook)
+    assert r["alpha_A"] > r["alpha_B"]
+    assert oracle.cross_section(13.6) == 6.30e-18
+    assert oracle.cross_section(13.5) == 0.0
+    # hydrogenic cross-section falls as E^-3.5 far above threshold (Born limit)
+    s1, s2 = oracle.cross_section(2e5), oracle.cross_section(4e5)
+    assert abs(math.log(s2 / s1) / math.log(2.0) + 3.5) < 0.02
+
+
+def _bb_number(a):
+    # int_a^inf x^2/(e^x - 1) dx in closed series form
+    return sum(math.exp(-k * a) * (a * a / k + 2 * a / k ** 2 + 2 / k ** 3) for k in range(1, 400))
+
+
+def _bb_energy(a):
+    # int_a^inf x^3/(e^x - 1) dx
+    return sum(math.exp(-k * a) * (a ** 3 / k + 3 * a * a / k ** 2 + 6 * a / k ** 3 + 6 / k ** 4)
+               for k in range(1, 400))
+
+
+def test_group_photon_fractions_and_mean_energies_closed_form():
+    kT = KB * E.T_BB / EV
+    edges = E.EDGES[3]
+    g = oracle.group_constants(E.T_BB, edges)
+    num = [_bb_number(e / kT) for e in edges]
+    en = [_bb_energy(e / kT) for e in edges]
+    tot = num[0] - num[-1]
+    for i in range(3):
+        n_i = num[i] - num[i + 1]
+        assert abs(g["frac"][i] - n_i / tot) < 1e-11
+        mean = kT * (en[i] - en[i + 1]) / n_i
+        assert abs(g["mean_E"][i] / EV / mean - 1) < 1e-11
+    assert abs(g["frac"].sum() - 1) < 1e-14
+
+
+def test_group_cross_sections_match_adaptive_quadrature():
+    # sigma_N and sigma_E (eq. e:siggroup and the sigma_E definition) against an
+    # adaptive Gauss-Kronrod quadrature of the same cross-section.
+    from scipy.integrate import quad
+    kT = KB * E.T_BB / EV
+    edges = E.EDGES[3]
+    g = oracle.group_constants(E.T_BB, edges)
+    for i in range(3):
+        a, b = edges[i], edges[i + 1]
+        nE = lambda e: e * e / math.expm1(e / kT)
+        I_n = quad(nE, a, b, epsabs=0, epsrel=1e-13, limit=200)[0]
+        I_s = quad(lambda e: oracle.cross_section(e) * nE(e), a, b, epsabs=0, epsrel=1e-13,
+                   limit=200)[0]
+        I_e = quad(lambda e: e * nE(e), a, b, epsabs=0, epsrel=1e-13, limit=200)[0]
+        I_se = quad(lambda e: oracle.cross_section(e) * e * nE(e), a, b, epsabs=0,
+                    epsrel=1e-13, limit=200)[0]
+        assert abs(g["sigma_N"][i] / (I_s / I_n) - 1) < 1e-10
+        assert abs(g["sigma_E"][i] / (I_se / I_e) - 1) < 1e-10
+
+
+def _x_eq(G_, n0, alpha, beta):
+    # positive root of a x^2 + b x - Gamma = 0, in the cancellation-free form
+    a = (alpha + beta) * n0
+    b = G_ - beta * n0
+    q = math.sqrt(b * b + 4 * a * G_)
+    return 2 * G_ / (b + q) if b > 0 else (q - b) / (2 * a)
+
+
+def test_ionisation_equilibrium_is_a_fixed_point():
+    # Eq. (e:therm3) at rest: (alpha+beta) n0 x^2 + (Gamma - beta n0) x - Gamma = 0.
+    # With S = kappa N the photon density is stationary too.
+    g = _groups(3)
+    c = 0.1 * C
+    T, n0 = 2e4, 3e-3
+    N = np.array([2e-3, 1e-3, 1e-4])
+    r = oracle.rates(T)
+    Gam = c * float(np.dot(g["sigma_N"], N))
+    xe = _x_eq(Gam, n0, r["alpha_B"], r["beta"])
+    S = c * g["sigma_N"] * (1 - xe) * n0 * N
+    F = np.zeros((3, 3))
+    N1, F1, x1, T1, cnt = oracle.chem_cell(N, F, xe, T, n0, S, dt=3e12, c_red=c, groups=g,
+                                           isothermal=1)
+    assert abs(x1 - xe) <= 1e-14
+    assert np.allclose(N1, N, rtol=1e-13)
+    assert T1 == T
+
+
+def test_coronal_equilibrium():
+    g = _groups(1)
+    T, n0 = 1.5e5, 1e-3
+    r = oracle.rates(T)
+    xe = r["beta"] / (r["alpha_B"] + r["beta"])
+    N1, F1, x1, T1, _ = oracle.chem_cell([0.0], np.zeros((1, 3)), xe, T, n0, [0.0], dt=1e15,
+                                         c_red=C, groups=g, isothermal=1)
+    assert abs(x1 - xe) <= 1e-14
+
+
+def test_photoionisation_of_neutral_gas_single_substep():
+    # x = 0, isothermal: no recombination term; the neutral fraction falls by the
+    # implicit factor 1/(1 + dt Gamma) with Gamma from the updated N.
+    g = _groups(3)
+    c = 0.1 * C
+    n0 = 1e-3
+    N = np.array([1e-2, 5e-3, 1e-3])
+    S = np.array([1e-12, 3e-13, 0.0])
+    dt = 1e10
+    N1, F1, x1, _, _ = oracle.chem_cell(N, np.ones((3, 3)), 0.0, 5000.0, n0, S, dt=dt,
+                                        c_red=c, groups=g, isothermal=1)
+    kap = c * g["sigma_N"] * n0
+    Nexp = (N + S * dt) / (1 + dt * kap)
+    assert np.allclose(N1, Nexp, rtol=1e-14)
+    assert np.allclose(F1, np.ones((3, 3)) / (1 + dt * kap)[:, None], rtol=1e-14)
+    Gam = c * float(np.dot(g["sigma_N"], Nexp))
+    assert abs((1 - x1) - 1 / (1 + dt * Gam)) < 1e-14
+
+
+def test_pure_recombination_converges_first_order():
+    # N = 0, T = 5000 K (collisional ionisation ~ 1e-27): x' = -alpha n0 x^2,
+    # x(t) = x0 / (1 + alpha n0 x0 t); the explicit-in-x update converges at first order.
+    g = _groups(1)
+    T, n0, x0, t = 5000.0, 1.0, 0.5, 4e12
+    a = oracle.rates(T)["alpha_B"]
+    exact = x0 / (1 + a * n0 * x0 * t)
+    errs = []
+    for nsteps in (50, 100, 200, 400):
+        N, F, x, TT = E.initial_state((1, 1, 1), 1, x0=x0, T0=T)
+        N, F, x, TT, _ = oracle.run(N, F, x, TT, np.full((1, 1, 1), n0), np.zeros(0, np.int64),
+                                    np.zeros(0), dx=1e20, c_red=C, dt=t / nsteps, n_steps=nsteps,
+                                    groups=g, isothermal=1)
+        errs.append(float(x[0, 0, 0]) - exact)
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(abs(r - 2) < 0.05 for r in ratios)
+    # Richardson extrapolation removes the first-order term
+    assert abs((2 * (exact + errs[3]) - (exact + errs[2])) - exact) < 0.02 * abs(errs[3])
+
+
+def test_substeps_tile_dt_and_respect_ten_percent_rule():
+    # Without absorber the source adds exactly S dt whatever the substep
+    # sequence (sum of dtau = dt); with strong heating e grows by at most 10 %
+    # per accepted substep, so the count is at least log(e1/e0)/log(1.1).
+    g = _groups(3)
+    g0 = dict(g, sigma_N=np.zeros(3))
+    c = 0.1 * C
+    S = np.array([3e-10, 2e-10, 1e-11])
+    N = np.zeros(3)
+    N1, _, _, _, cnt = oracle.chem_cell(N, np.zeros((3, 3)), 1.2e-3, 100.0, 1e-3, S, dt=7e9,
+                                        c_red=c, groups=g0)
+    assert np.allclose(N1, S * 7e9, rtol=1e-14)
+    N = np.array([1.0, 0.8, 0.05])
+    x0, T0, n0 = 1.2e-3, 100.0, 1e-3
+    N1, _, x1, T1, cnt = oracle.chem_cell(N, np.zeros((3, 3)), x0, T0, n0, S, dt=7e9,
+                                          c_red=c, groups=g)
+    e0 = 1.5 * (1 + x0) * n0 * KB * T0
+    e1 = 1.5 * (1 + x1) * n0 * KB * T1
+    assert e1 > 10 * e0
+    assert cnt["substeps"] >= math.log(e1 / e0) / math.log(1.1)
+    assert cnt["attempts"] > cnt["substeps"]          # halvings happened
+    assert cnt["cap_hits"] == 0
+
+
+def test_substep_cap_is_reported():
+    g = _groups(1)
+    N1, _, x1, T1, cnt = oracle.chem_cell([1.0], np.zeros((1, 3)), 1.2e-3, 100.0, 1e-3, [0.0],
+                                          dt=7e9, c_red=0.1 * C, groups=g, max_substeps=3)
+    assert cnt["cap_hits"] == 1 and cnt["substeps"] == 4
+
+
+# --------------------------------------------------------------- Stromgren
+
+@pytest.mark.slow
+def test_stromgren_equilibrium_isothermal():
+    # Monochromatic 13.6 eV point source in uniform isothermal (1e4 K) gas on the
+    # spot (the static-gas HII-region test of Sec. 6): once the photon field is
+    # steady every emitted photon is absorbed, and the net recombination rate
+    # approaches the emission rate, so the ionised volume tends to the
+    # Stromgren volume 4/3 pi R_s^3, R_s = (3 Ndot / (4 pi n^2 alpha_B))^(1/3).
+    n, box = 16, 13.2 * E.KPC
+    dx = box / n
+    c = 1e-3 * C
+    dt = E.courant_dt(dx, c)
+    Ndot, n0v, T = 5e48, 1e-3, 1e4
+    g = {"sigma_N": [6.30e-18], "sigma_E": [6.30e-18], "mean_E": [13.6 * EV], "frac": [1.0]}
+    r = oracle.rates(T)
+    aB, beta = r["alpha_B"], r["beta"]
+    Rs = (3 * Ndot / (4 * math.pi * n0v ** 2 * aB)) ** (1 / 3)
+    t_rec = 1 / (aB * n0v)
+    steps = int(8 * t_rec / dt) + 1
+    N, F, x, TT = E.initial_state((n, n, n), 1, x0=1.2e-3, T0=T)
+    n0 = np.full((n, n, n), n0v)
+    cell = np.array([(8 * n + 8) * n + 8])
+    N, F, x, TT, cnt = oracle.run(N, F, x, TT, n0, cell, np.array([Ndot]), dx=dx, c_red=c,
+                                  dt=dt, n_steps=steps, groups=g, isothermal=1)
+    vol = dx ** 3
+    absorbed = (c * 6.30e-18 * (1 - x) * n0v * N[0]).sum() * vol
+    assert abs(absorbed / Ndot - 1) < 1e-4
+    net_rec = ((aB * x * x - beta * x * (1 - x)) * n0v ** 2).sum() * vol
+    assert abs(net_rec / Ndot - 1) < 0.015
+    R = (3 * x.sum() * vol / (4 * math.pi)) ** (1 / 3)
+    assert abs(R / Rs - 1) < 0.08
+
+
+def test_stromgren32_early_front_bounded_by_photon_count():
+    # 200 steps of the 32^3 Stromgren workload: no more atoms ionised than
+    # photons emitted, and the ionised volume far below the Stromgren volume.
+    w = E.make_workload("stromgren32", n=16)
+    g = _groups(1)
+    steps = 40
+    N, F, x, T, cnt = oracle.run(w["N"], w["F"], w["x"], w["T"], w["n0"], w["src_cell"],
+                                 w["src_rate"], dx=w["dx"], c_red=w["c_red"], dt=w["dt"],
+                                 n_steps=steps, groups=g)
+    vol = w["dx"] ** 3
+    ionised = ((x - 1.2e-3) * w["n0"]).sum() * vol
+    emitted = w["src_rate"].sum() * steps * w["dt"]
+    assert 0 < ionised <= emitted
+    assert ionised + N.sum() * vol <= emitted * (1 + 1e-6)
+    assert cnt["limiter"] == 0 and cnt["neg_clamp"] == 0
