@@ -1,0 +1,190 @@
+"""Throughput of the M1 transport + thermochemistry step on one MI355X.
+
+Workload (default): 256^3 periodic grid, 3 photon groups (13.6/24.6/54.4/1000 eV,
+1e5 K black body), log-normal hydrogen density (sigma_ln = 1, mean 1e-3 cm^-3,
+P(k) ~ k^-2, seed 3), 256 point sources at random cells with log-uniform rates
+1e47-1e50 photons/s, c_red = 0.1 c, dt = 0.8 dx / (3 c_red), from a dark, cold
+(100 K), nearly neutral (x = 1.2e-3) start.  A step is one pass of the whole
+path: source table (once per call), transport of all groups, chemistry subcycle.
+
+Prints ONE JSON line: cell-updates/s of the FP32-transport / FP64-chemistry
+path (the metric), the all-FP64 path on the same inputs, the roofline figure of
+the dominant kernel (algorithmic bytes per launch over its event-timed average
+duration), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+
+
+def algorithmic_bytes(kernel, G, elem):
+    """Bytes a kernel must move per cell: each field read or written once.
+    N, F: 4 G values of `elem` bytes; x, T, n0: doubles."""
+    nf = 4 * G * elem
+    if kernel == "transport":
+        return 2 * nf
+    if kernel in ("chemistry", "fused_step"):
+        return 2 * nf + 3 * 8 + 2 * 8
+    return None
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1508_07888_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when there is none or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_1508_07888_amd import EmmaRT
+    dev = "cuda:0"
+    G = w["G"]
+    rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"],
+                edges_eV=w["edges"], device=dev)
+    fdt = rt.dtype
+    N0 = torch.tensor(w["N"], dtype=fdt, device=dev)
+    F0 = torch.tensor(w["F"], dtype=fdt, device=dev)
+    x0 = torch.tensor(w["x"], dtype=torch.float64, device=dev)
+    T0 = torch.tensor(w["T"], dtype=torch.float64, device=dev)
+    n0 = torch.tensor(w["n0"], dtype=torch.float64, device=dev)
+    cells = torch.tensor(w["src_cell"], dtype=torch.int64, device=dev)
+    rates = torch.tensor(w["src_rate"], dtype=torch.float64, device=dev)
+    N, F, x, T = N0.clone(), F0.clone(), x0.clone(), T0.clone()
+    if warmup > 0:
+        rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=warmup)
+    # timed: K steps from the initial state, inputs resident in HBM
+    N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
+    rt.profile(True)
+    rt.profile_read()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(rt.stream)
+    rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=steps)
+    stop.record(rt.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    kern = rt.profile_read()
+    rt.profile(False)
+    # untimed diagnostic pass over the same steps (substep statistics)
+    N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
+    d = rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=steps, diag=True,
+                raise_on_status=False)
+    torch.cuda.synchronize()
+    rt.close()
+    V = N0[0].numel()
+    return dict(ms=ms, value=V * steps / (ms * 1e-3), ms_per_step=ms / steps, kernels=kern,
+                diag=d, V=V, elem=4 if precision == "mixed" else 8)
+
+
+def cpu_baseline(w, budget_steps=1):
+    """The oracle, untuned and serial, on the first step of the same inputs."""
+    import oracle
+    g = oracle.group_constants(w["T_bb"], w["edges"])
+    t = time.perf_counter()
+    oracle.run(w["N"], w["F"], w["x"], w["T"], w["n0"], w["src_cell"], w["src_rate"],
+               dx=w["dx"], c_red=w["c_red"], dt=w["dt"], n_steps=budget_steps, groups=g)
+    s = time.perf_counter() - t
+    V = w["n0"].size
+    return {"value": V * budget_steps / s, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {budget_steps} step(s) of the same {w['shape'][0]}^3 inputs, "
+                      f"serial FP64 oracle (g++ -O2), {s:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="throughput256")
+    ap.add_argument("--n", type=int, default=None, help="override the grid size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the radiation step is built and timed on a "
+              "single MI355X (no multi-GPU path in this build); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import emma_inputs as E
+    w = E.make_workload(args.workload, n=args.n)
+    G = w["G"]
+    mixed = run_gpu(w, "mixed", args.steps, args.warmup)
+    fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup)
+
+    kern = mixed["kernels"]
+    dom = max((k for k in kern if k != "src_table"), key=lambda k: kern[k][1])
+    launches, total_ms = kern[dom]
+    avg_s = total_ms / launches * 1e-3
+    per_cell = algorithmic_bytes(dom, G, mixed["elem"])
+    bytes_launch = per_cell * mixed["V"]
+    achieved = bytes_launch / avg_s
+    traffic = traffic_from_profiles(dom, args.workload, "mixed")
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": traffic, "kernel": dom,
+                "bytes_per_cell": per_cell, "avg_launch_ms": avg_s * 1e3}
+    out = {
+        "metric": "M1+chem cell-updates/s at 256^3x3 groups (FP32 transport + FP64 chemistry)",
+        "value": mixed["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": w["shape"][0], "groups": G,
+                   "sources": int(w["src_cell"].size), "c_red_over_c": w["c_red"] / E.C_LIGHT,
+                   "precision": "mixed"},
+        "roofline": roofline,
+        "group_cell_updates_per_s": mixed["value"] * G,
+        "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()},
+        "substeps_per_cell_step": mixed["diag"]["substeps"] / (mixed["V"] * args.steps),
+        "attempts_per_cell_step": mixed["diag"]["attempts"] / (mixed["V"] * args.steps),
+        "max_substeps_cell_step": mixed["diag"]["max_sub"],
+    }
+    if fp64 is not None:
+        k64 = fp64["kernels"]
+        dom64 = max((k for k in k64 if k != "src_table"), key=lambda k: k64[k][1])
+        b64 = algorithmic_bytes(dom64, G, 8) * fp64["V"]
+        a64 = b64 / (k64[dom64][1] / k64[dom64][0] * 1e-3)
+        out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+                       "dtype": "f64", "kernel": dom64, "achieved_GBs": a64 / 1e9,
+                       "frac": a64 / HBM_PEAK,
+                       "kernels_ms": {k: v[1] / v[0] for k, v in k64.items()}}
+        out["mixed_over_fp64"] = mixed["value"] / fp64["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * emma_rt.h -- C ABI of the MI355X radiation step library (libemma_rt.so).
+ *
+ * One call advances the coarse-grid radiation of the EMMA code (Aubert,
+ * Deparis & Ocvirk 2015) by n_steps explicit steps on a uniform periodic grid
+ * with the gas frozen, as the coarse radiative transport approximation (Sec. 5)
+ * does between two dynamical steps.  Each step is
+ *   1. the M1 transport of every frequency group (Sec. 2.2.3): Eddington
+ *      tensor closure, Lax-Friedrichs / HLL(+-c_red) face fluxes (eq. e:glf)
+ *      and the unsplit conservative update (eq. e:uprt), then
+ *   2. the per-cell sub-cycled hydrogen thermochemistry (Sec. 2.2.4):
+ *      source injection, photo-ionisation, recombination, collisional
+ *      ionisation, heating and cooling, coupled back into N and F.
+ *
+ * Conventions for every entry point
+ *   - Field pointers are HIP device memory owned by the caller.  Layout is C
+ *     order with x fastest: N[G][nz][ny][nx], F[G][3][nz][ny][nx] (component
+ *     major), x_HII, T, n_H [nz][ny][nx].  Cell index = (z*ny + y)*nx + x.
+ *   - Units CGS: N photons cm^-3, F photons cm^-2 s^-1, T K, n_H cm^-3 (the
+ *     TOTAL hydrogen density n0; the neutral density is (1-x_HII) n0), dx cm,
+ *     dt s, c_red cm s^-1, source rates photons s^-1.
+ *   - Storage: EMMA_RT_FP64 keeps N, F in double; EMMA_RT_MIXED keeps N, F in
+ *     float (transport computed in float, chemistry in double).  x_HII, T and
+ *     n_H are always double.
+ *   - Calls are asynchronous on the context's stream; only a call given a
+ *     non-NULL diag waits for its own work.  Calls on one context must not
+ *     overlap (the context owns scratch that every call reuses).
+ *   - Errors are returned as emma_rt_status codes; nothing aborts or throws
+ *     across the ABI.  emma_rt_last_error() gives the context's last message.
+ */
+#ifndef EMMA_RT_H
+#define EMMA_RT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct emma_rt_ctx emma_rt_ctx;
+
+typedef enum {
+    EMMA_RT_OK = 0,
+    EMMA_RT_EINVAL = -1,     /* bad argument; nothing was launched */
+    EMMA_RT_ENOMEM = -2,     /* device allocation failed (init only) */
+    EMMA_RT_EHIP = -3,       /* a HIP runtime call failed */
+    EMMA_RT_ESUBSTEP = -4,   /* chemistry guard fired in some cell (diag only);
+                                outputs are written, count in diag->cap_hits */
+    EMMA_RT_ENONFINITE = -5  /* NaN/Inf found in the end state (diag only) */
+} emma_rt_status;
+
+typedef enum { EMMA_RT_FP64 = 0, EMMA_RT_MIXED = 1 } emma_rt_precision;
+
+#define EMMA_RT_MAX_GROUPS 4
+#define EMMA_RT_MAX_SOURCES 65536
+
+typedef struct {
+    int32_t nx, ny, nz;         /* grid, each >= 1 */
+    int32_t n_groups;           /* 1 .. EMMA_RT_MAX_GROUPS frequency groups */
+    double dx;                  /* cell size, cm */
+    double c_red;               /* reduced speed of light (Sec. 2.2.3), 0 < c_red <= c */
+    int32_t precision;          /* emma_rt_precision */
+    int32_t otsa;               /* 1: on-the-spot (alpha_A := alpha_B, no recombination
+                                   photons); 0: case A with recombination photons
+                                   into group 1 (eq. e:therm1g) */
+    int32_t isothermal;         /* 1: validation mode, one substep of dt, T frozen */
+    int32_t max_substeps;       /* accepted substeps per cell per step before the
+                                   guard takes one last substep of the remainder */
+    int32_t adjoint_max_steps;  /* K: longest segment emma_rt_step_adjoint accepts;
+                                   0 = no adjoint scratch */
+    int32_t reserved;
+    /* Per-group constants (Sec. 2.2.3-2.2.4, eq. e:siggroup and the sigma_E and
+       <E> definitions): number- and energy-weighted cross-sections (cm^2), mean
+       photon energy (erg) and fraction of a source's photons in the group. */
+    double sigma_N[EMMA_RT_MAX_GROUPS];
+    double sigma_E[EMMA_RT_MAX_GROUPS];
+    double mean_E[EMMA_RT_MAX_GROUPS];
+    double src_frac[EMMA_RT_MAX_GROUPS];
+} emma_rt_config;
+
+typedef struct {
+    double photons[EMMA_RT_MAX_GROUPS]; /* sum over cells of N dx^3, end state */
+    double ionised;                     /* sum over cells of x_HII n_H dx^3 */
+    int64_t substeps;                   /* accepted chemistry substeps, all cells and steps */
+    int64_t attempts;                   /* substep attempts including 10 % halvings */
+    int32_t max_sub;                    /* most accepted substeps of one cell in one step */
+    int32_t reserved;
+    int64_t limiter_hits;               /* transport: |F*| > c N* rescaled */
+    int64_t neg_clamps;                 /* transport: N* < 0 set to 0 */
+    int64_t x_clamps;                   /* chemistry: x_HII clamped to [0, 1] */
+    int64_t cap_hits;                   /* chemistry: cells where the substep guard fired */
+    int64_t nonfinite;                  /* cells with a NaN/Inf in the end state */
+} emma_rt_diag;
+
+/* Create a context on the current HIP device.  cfg is copied.  hip_stream is a
+ * hipStream_t (NULL = the default stream).  Allocates every piece of scratch
+ * the later calls use (transport ping-pong fields, source tables, counters,
+ * adjoint tape of adjoint_max_steps steps).  Returns EINVAL for a bad config,
+ * ENOMEM when the scratch does not fit; *ctx is NULL on any error. */
+int emma_rt_init(emma_rt_ctx **ctx, const emma_rt_config *cfg, void *hip_stream);
+
+/* Advance (N, F, x_HII, T) in place by n_steps steps of dt (Sec. 2.2.3-2.2.4,
+ * Sec. 5), with the gas density n_H and the source list held fixed.
+ *   N, F            device, float or double per precision, read and written
+ *   x_HII, T        device double, read and written
+ *   n_H             device double, read only
+ *   src_cell        device int64 [n_src], flat cell index of each point source
+ *   src_rate        device double [n_src], photons s^-1; sources sharing a cell add
+ *   dt              must satisfy 0 < dt <= dx / (3 c_red) (positivity of the
+ *                   unsplit 3D update); larger dt returns EINVAL
+ *   diag            NULL: no reductions, no wait.  Else filled after the call waits.
+ * Returns OK, EINVAL, EHIP, or (diag only) ESUBSTEP / ENONFINITE. */
+int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
+                 const double *n_H, const int64_t *src_cell, const double *src_rate,
+                 int32_t n_src, double dt, int32_t n_steps, emma_rt_diag *diag);
+
+/* Vector-Jacobian product of n_steps steps (1 <= n_steps <= adjoint_max_steps),
+ * the exact derivative of the discrete map computed by emma_rt_step along the
+ * branches (substep lengths, halvings, clamps) that the forward run takes.
+ *   N0, F0, x0, T0  device, the state at the start of the segment (not modified)
+ *   gN, gF, gx, gT  device, same layouts as the state (gN, gF in the state's
+ *                   precision): on entry dL/d(state at segment end), on exit
+ *                   dL/d(state at segment start)
+ *   g_nH            device double [cells], dL/dn_H is ADDED to it
+ *   g_src_rate      device double [n_src], dL/d(src_rate) is ADDED to it
+ * The segment is recomputed forward from (N0, F0, x0, T0) into the context's
+ * tape.  Returns OK, EINVAL or EHIP. */
+int emma_rt_step_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
+                         const double *x0, const double *T0, const double *n_H,
+                         const int64_t *src_cell, const double *src_rate, int32_t n_src,
+                         double dt, int32_t n_steps,
+                         void *gN, void *gF, double *gx, double *gT,
+                         double *g_nH, double *g_src_rate);
+
+/* Release the context and all its device scratch.  NULL is a no-op. */
+void emma_rt_free(emma_rt_ctx *ctx);
+
+/* Message of the context's most recent error ("" if none); a static message
+ * when ctx is NULL (e.g. after a failed init). */
+const char *emma_rt_last_error(const emma_rt_ctx *ctx);
+
+/* Group constants of a black-body source spectrum of temperature T_bb (K) over
+ * the group edges edges_eV[0..G] (Sec. 2.2.3-2.2.4): sigma_N, sigma_E (cm^2),
+ * mean_E (erg) and the photon fraction of each group, by Gauss-Legendre
+ * quadrature of the hydrogen photo-ionisation cross-section.  Host memory.
+ * Returns EINVAL for G outside 1..EMMA_RT_MAX_GROUPS or unsorted edges. */
+int emma_rt_group_constants(double T_bb, const double *edges_eV, int32_t G,
+                            double *sigma_N, double *sigma_E, double *mean_E,
+                            double *src_frac);
+
+/* Per-kernel timing.  While enabled, every kernel that emma_rt_step and
+ * emma_rt_step_adjoint launch is bracketed by HIP events recorded on the
+ * context's stream (a few microseconds of overhead per launch; the events
+ * are created here, not in the step).  emma_rt_profile_read waits for the
+ * stream, returns one record per kernel kind that ran since the last read
+ * (name, launches, summed duration in ms) and resets the sums.  Host memory;
+ * *n_out is the number of records written (at most max_out).  Returns EINVAL
+ * for a NULL context, EHIP on a runtime failure. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} emma_rt_kernel_time;
+
+int emma_rt_profile_enable(emma_rt_ctx *ctx, int32_t enable);
+int emma_rt_profile_read(emma_rt_ctx *ctx, emma_rt_kernel_time *out, int32_t max_out,
+                         int32_t *n_out);
+
+/* Size in bytes of the device scratch a context with this config allocates. */
+int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMMA_RT_H */

@@ -1,0 +1,565 @@
+// emma_rt.hip -- C ABI of the MI355X radiation step library (include/emma_rt.h).
+//
+// Host side: argument checks, scratch ownership, the per-call source table,
+// the step loop and the diagnostics.  Every step of the path runs in the HIP
+// kernels of kernels.hpp / fused.hpp / adjoint.hpp; nothing falls back to the
+// host.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/emma_rt.h"
+#include "kernels.hpp"
+#include "fused.hpp"
+#include "adjoint.hpp"
+
+using namespace emma;
+
+struct emma_rt_ctx {
+    emma_rt_config cfg;
+    hipStream_t stream;
+    int device;
+    Grid grid;
+    size_t elem;           // bytes per N/F element (4 or 8)
+    void *Ns, *Fs;         // transport output / fused ping-pong (storage precision)
+    uint32_t *mask;        // one bit per cell: cell hosts a source
+    int64_t mask_words;
+    int64_t *sorted_cell;  // [EMMA_RT_MAX_SOURCES]
+    int32_t *sorted_idx;
+    double *S;             // [EMMA_RT_MAX_SOURCES][G]
+    unsigned long long *cnt;     // [CNT_COUNT]
+    double *partial;             // [nblk][G+1]
+    int diag_blocks;
+    double *dsum;                // [G+1]
+    AdjointScratch adj;
+    int use_fused;               // 1: fused transport+chemistry kernel
+    // kernel timing (emma_rt_profile_enable)
+    int prof;
+    std::vector<hipEvent_t> *ev;     // pool, pairs (start, stop)
+    std::vector<int> *ev_kind;       // kernel kind of each pair in flight
+    double prof_ms[KID_COUNT];
+    int64_t prof_n[KID_COUNT];
+    char err[512];
+};
+
+static char g_static_err[512] = "";
+
+static int fail(emma_rt_ctx *c, int code, const char *fmt, ...) {
+    char *buf = c ? c->err : g_static_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), EMMA_RT_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static int check_launch(emma_rt_ctx *c, const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, EMMA_RT_EHIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return EMMA_RT_OK;
+}
+
+// ---------------------------------------------------------- kernel timing
+static const int kEventPairs = 512;
+
+static int prof_flush(emma_rt_ctx *c) {
+    const int n = (int)c->ev_kind->size();
+    if (n == 0) return EMMA_RT_OK;
+    HIP_TRY(c, hipEventSynchronize((*c->ev)[2 * n - 1]));
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, (*c->ev)[2 * i], (*c->ev)[2 * i + 1]));
+        c->prof_ms[(*c->ev_kind)[i]] += ms;
+        c->prof_n[(*c->ev_kind)[i]] += 1;
+    }
+    c->ev_kind->clear();
+    return EMMA_RT_OK;
+}
+
+// Brackets one launch with events when timing is on.
+struct Timed {
+    emma_rt_ctx *c;
+    int kind;
+    bool on;
+    Timed(emma_rt_ctx *c_, int kind_) : c(c_), kind(kind_), on(c_->prof != 0) {
+        if (!on) return;
+        if ((int)c->ev_kind->size() == kEventPairs) prof_flush(c);
+        const int i = (int)c->ev_kind->size();
+        (void)hipEventRecord((*c->ev)[2 * i], c->stream);
+    }
+    ~Timed() {
+        if (!on) return;
+        const int i = (int)c->ev_kind->size();
+        (void)hipEventRecord((*c->ev)[2 * i + 1], c->stream);
+        c->ev_kind->push_back(kind);
+    }
+};
+
+static GroupConsts group_consts(const emma_rt_config &cfg) {
+    GroupConsts gc;
+    for (int g = 0; g < 4; ++g) {
+        const bool on = g < cfg.n_groups;
+        gc.sigN[g] = on ? cfg.sigma_N[g] : 0.0;
+        gc.SigE[g] = on ? cfg.sigma_E[g] * cfg.mean_E[g] - cfg.sigma_N[g] * kE13 : 0.0;
+        gc.frac[g] = on ? cfg.src_frac[g] : 0.0;
+    }
+    return gc;
+}
+
+static const char *config_error(const emma_rt_config *cfg) {
+    if (!cfg) return "config is NULL";
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return "grid dimensions must be >= 1";
+    if ((int64_t)cfg->nx * cfg->ny * cfg->nz > ((int64_t)1 << 34)) return "grid too large";
+    if (cfg->n_groups < 1 || cfg->n_groups > EMMA_RT_MAX_GROUPS) return "n_groups must be in 1..4";
+    if (!(cfg->dx > 0) || !isfinite(cfg->dx)) return "dx must be > 0";
+    if (!(cfg->c_red > 0) || cfg->c_red > kC * (1 + 1e-12)) return "c_red must be in (0, c]";
+    if (cfg->precision != EMMA_RT_FP64 && cfg->precision != EMMA_RT_MIXED) return "bad precision";
+    if (cfg->max_substeps < 1) return "max_substeps must be >= 1";
+    if (cfg->adjoint_max_steps < 0) return "adjoint_max_steps must be >= 0";
+    for (int g = 0; g < cfg->n_groups; ++g) {
+        if (!(cfg->sigma_N[g] >= 0) || !(cfg->sigma_E[g] >= 0) || !(cfg->mean_E[g] >= 0) ||
+            !(cfg->src_frac[g] >= 0))
+            return "group constants must be finite and >= 0";
+    }
+    return nullptr;
+}
+
+static int64_t field_bytes(const emma_rt_config *cfg) {
+    const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    const int64_t e = cfg->precision == EMMA_RT_FP64 ? 8 : 4;
+    return 4 * cfg->n_groups * V * e;  // N and F of all groups
+}
+
+extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
+    if (config_error(cfg)) return -1;
+    const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    int64_t b = field_bytes(cfg);                          // Ns + Fs
+    b += ((V + 31) / 32) * 4;                              // mask
+    b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
+    b += CNT_COUNT * 8;
+    b += ((V + 255) / 256) * (cfg->n_groups + 1) * 8 + (cfg->n_groups + 1) * 8;
+    b += adjoint_scratch_bytes(*cfg);
+    return b;
+}
+
+static void release(emma_rt_ctx *c) {
+    if (!c) return;
+    (void)hipFree(c->Ns);
+    (void)hipFree(c->Fs);
+    (void)hipFree(c->mask);
+    (void)hipFree(c->sorted_cell);
+    (void)hipFree(c->sorted_idx);
+    (void)hipFree(c->S);
+    (void)hipFree(c->cnt);
+    (void)hipFree(c->partial);
+    (void)hipFree(c->dsum);
+    adjoint_release(c->adj);
+    if (c->ev) {
+        for (hipEvent_t e : *c->ev) (void)hipEventDestroy(e);
+        delete c->ev;
+        delete c->ev_kind;
+        c->ev = nullptr;
+        c->ev_kind = nullptr;
+    }
+}
+
+extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *stream) {
+    if (!out) return fail(nullptr, EMMA_RT_EINVAL, "ctx out-pointer is NULL");
+    *out = nullptr;
+    if (const char *why = config_error(cfg)) return fail(nullptr, EMMA_RT_EINVAL, "%s", why);
+    emma_rt_ctx *c = new (std::nothrow) emma_rt_ctx();
+    if (!c) return fail(nullptr, EMMA_RT_ENOMEM, "host allocation failed");
+    memset(c, 0, sizeof(*c));
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)stream;
+    c->grid.nx = cfg->nx;
+    c->grid.ny = cfg->ny;
+    c->grid.nz = cfg->nz;
+    c->grid.V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    c->elem = cfg->precision == EMMA_RT_FP64 ? 8 : 4;
+    c->use_fused = fused_supported(c->grid) ? 1 : 0;
+    (void)hipGetDevice(&c->device);
+    const int64_t V = c->grid.V;
+    const int G = cfg->n_groups;
+    c->mask_words = (V + 31) / 32;
+    c->diag_blocks = (int)((V + 255) / 256);
+    struct { void **p; size_t n; } allocs[] = {
+        {&c->Ns, (size_t)(G * V) * c->elem},
+        {&c->Fs, (size_t)(3 * G * V) * c->elem},
+        {(void **)&c->mask, (size_t)c->mask_words * 4},
+        {(void **)&c->sorted_cell, (size_t)EMMA_RT_MAX_SOURCES * 8},
+        {(void **)&c->sorted_idx, (size_t)EMMA_RT_MAX_SOURCES * 4},
+        {(void **)&c->S, (size_t)EMMA_RT_MAX_SOURCES * G * 8},
+        {(void **)&c->cnt, (size_t)CNT_COUNT * 8},
+        {(void **)&c->partial, (size_t)c->diag_blocks * (G + 1) * 8},
+        {(void **)&c->dsum, (size_t)(G + 1) * 8},
+    };
+    for (auto &a : allocs) {
+        if (hipMalloc(a.p, a.n) != hipSuccess) {
+            (void)hipGetLastError();
+            release(c);
+            delete c;
+            return fail(nullptr, EMMA_RT_ENOMEM, "hipMalloc of %zu bytes failed", a.n);
+        }
+    }
+    if (adjoint_alloc(c->adj, *cfg) != 0) {
+        (void)hipGetLastError();
+        release(c);
+        delete c;
+        return fail(nullptr, EMMA_RT_ENOMEM, "adjoint tape allocation failed");
+    }
+    c->err[0] = 0;
+    *out = c;
+    return EMMA_RT_OK;
+}
+
+extern "C" void emma_rt_free(emma_rt_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+extern "C" const char *emma_rt_last_error(const emma_rt_ctx *c) { return c ? c->err : g_static_err; }
+
+// ------------------------------------------------------------ source table
+template <int G>
+static int build_sources(emma_rt_ctx *c, const int64_t *cell, const double *rate, int n) {
+    const int tb = 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((c->mask_words + tb - 1) / tb)), dim3(tb), 0,
+                       c->stream, c->mask, c->mask_words, 0u);
+    if (int e = check_launch(c, "k_fill_u32")) return e;
+    if (n == 0) return EMMA_RT_OK;
+    Timed tr(c, KID_SRC);
+    hipLaunchKernelGGL(k_src_rank, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, cell, n, c->grid.V,
+                       c->sorted_cell, c->sorted_idx, c->cnt);
+    if (int e = check_launch(c, "k_src_rank")) return e;
+    const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
+    hipLaunchKernelGGL(k_src_heads<G>, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, c->sorted_cell,
+                       c->sorted_idx, rate, n, group_consts(c->cfg), 0.0, vol, c->S, c->mask);
+    return check_launch(c, "k_src_heads");
+}
+
+// --------------------------------------------------------------- step loop
+template <int G, typename S, bool DIAG>
+static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const double *n0, int n_src,
+                     double dt, int n_steps) {
+    const Grid gr = c->grid;
+    const int64_t V = gr.V;
+    const int tb = 256;
+    const unsigned nblk = (unsigned)((V + tb - 1) / tb);
+    const GroupConsts gc = group_consts(c->cfg);
+    ChemParams cp;
+    cp.c = c->cfg.c_red;
+    cp.dt = dt;
+    cp.otsa = c->cfg.otsa;
+    cp.isothermal = c->cfg.isothermal;
+    cp.max_substeps = c->cfg.max_substeps;
+    SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
+    S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
+    const S cr = (S)c->cfg.c_red;
+    const S lam = (S)(dt / c->cfg.dx);
+    if (c->use_fused) {
+        // ping-pong: even steps read the caller's buffers, odd steps the scratch
+        for (int s = 0; s < n_steps; ++s) {
+            const bool even = (s & 1) == 0;
+            S *iN = even ? N : Ns, *iF = even ? F : Fs;
+            S *oN = even ? Ns : N, *oF = even ? Fs : F;
+            int e;
+            {
+                Timed t(c, KID_FUSED);
+                e = launch_fused<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
+                                             dt / c->cfg.dx, c->cnt);
+            }
+            if (e) return fail(c, EMMA_RT_EHIP, "fused kernel launch failed: %s",
+                               hipGetErrorString(hipGetLastError()));
+        }
+        if (n_steps & 1) {
+            HIP_TRY(c, hipMemcpyAsync(N, Ns, (size_t)G * V * sizeof(S), hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(F, Fs, (size_t)3 * G * V * sizeof(S), hipMemcpyDeviceToDevice, c->stream));
+        }
+        return EMMA_RT_OK;
+    }
+    for (int s = 0; s < n_steps; ++s) {
+        {
+            Timed t(c, KID_TRANSPORT);
+            hipLaunchKernelGGL((k_transport<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, N, F, Ns,
+                               Fs, gr, cr, lam, c->cnt);
+        }
+        if (int e = check_launch(c, "k_transport")) return e;
+        {
+            Timed t(c, KID_CHEM);
+            hipLaunchKernelGGL((k_chem<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F, x,
+                               T, n0, V, src, gc, cp, c->cnt);
+        }
+        if (int e = check_launch(c, "k_chem")) return e;
+    }
+    return EMMA_RT_OK;
+}
+
+template <int G, typename S>
+static int diag_finish(emma_rt_ctx *c, const S *N, const S *F, const double *x, const double *T,
+                       const double *n0, emma_rt_diag *d) {
+    hipLaunchKernelGGL((k_diag_partial<G, S>), dim3(c->diag_blocks), dim3(256), 0, c->stream, N, F, x, T,
+                       n0, c->grid.V, c->partial, c->cnt);
+    if (int e = check_launch(c, "k_diag_partial")) return e;
+    hipLaunchKernelGGL((k_diag_final<G>), dim3(1), dim3(256), 0, c->stream, c->partial, c->diag_blocks,
+                       c->dsum);
+    if (int e = check_launch(c, "k_diag_final")) return e;
+    unsigned long long cnt[CNT_COUNT];
+    double sums[EMMA_RT_MAX_GROUPS + 1];
+    HIP_TRY(c, hipMemcpyAsync(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(sums, c->dsum, (G + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
+    memset(d, 0, sizeof(*d));
+    for (int g = 0; g < G; ++g) d->photons[g] = sums[g] * vol;
+    d->ionised = sums[G] * vol;
+    d->substeps = (int64_t)cnt[CNT_SUB];
+    d->attempts = (int64_t)cnt[CNT_ATT];
+    d->max_sub = (int32_t)cnt[CNT_MAXSUB];
+    d->limiter_hits = (int64_t)cnt[CNT_LIMITER];
+    d->neg_clamps = (int64_t)cnt[CNT_NEG];
+    d->x_clamps = (int64_t)cnt[CNT_XCLAMP];
+    d->cap_hits = (int64_t)cnt[CNT_CAP];
+    d->nonfinite = (int64_t)cnt[CNT_NONFINITE];
+    if (cnt[CNT_BADSRC]) return fail(c, EMMA_RT_EINVAL, "%llu source cell indices outside the grid were ignored",
+                                     cnt[CNT_BADSRC]);
+    if (d->nonfinite) return fail(c, EMMA_RT_ENONFINITE, "%lld cells hold NaN/Inf", (long long)d->nonfinite);
+    if (d->cap_hits) return fail(c, EMMA_RT_ESUBSTEP, "substep guard fired in %lld cell-steps",
+                                 (long long)d->cap_hits);
+    return EMMA_RT_OK;
+}
+
+template <int G, typename S>
+static int step_typed(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const double *n0,
+                      const int64_t *cell, const double *rate, int n_src, double dt, int n_steps,
+                      emma_rt_diag *d) {
+    if (d) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->cnt, (int)CNT_COUNT, 0ull);
+        if (int e = check_launch(c, "k_fill_u64")) return e;
+    }
+    if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
+    int e = d ? run_steps<G, S, true>(c, N, F, x, T, n0, n_src, dt, n_steps)
+              : run_steps<G, S, false>(c, N, F, x, T, n0, n_src, dt, n_steps);
+    if (e) return e;
+    if (d) return diag_finish<G, S>(c, N, F, x, T, n0, d);
+    return EMMA_RT_OK;
+}
+
+extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double *T, const double *n0,
+                            const int64_t *cell, const double *rate, int32_t n_src, double dt,
+                            int32_t n_steps, emma_rt_diag *d) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (!N || !F || !x || !T || !n0) return fail(c, EMMA_RT_EINVAL, "a field pointer is NULL");
+    if (n_src < 0 || n_src > EMMA_RT_MAX_SOURCES)
+        return fail(c, EMMA_RT_EINVAL, "n_src must be in 0..%d", EMMA_RT_MAX_SOURCES);
+    if (n_src > 0 && (!cell || !rate)) return fail(c, EMMA_RT_EINVAL, "source arrays are NULL");
+    if (n_steps < 0) return fail(c, EMMA_RT_EINVAL, "n_steps must be >= 0");
+    if (!(dt > 0) || !isfinite(dt)) return fail(c, EMMA_RT_EINVAL, "dt must be > 0");
+    if (dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
+        return fail(c, EMMA_RT_EINVAL, "dt = %g exceeds dx/(3 c_red) = %g", dt, c->cfg.dx / (3.0 * c->cfg.c_red));
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
+    c->err[0] = 0;
+    const int G = c->cfg.n_groups;
+    const bool f64 = c->cfg.precision == EMMA_RT_FP64;
+#define DISPATCH(GG)                                                                                      \
+    case GG:                                                                                              \
+        return f64 ? step_typed<GG, double>(c, (double *)N, (double *)F, x, T, n0, cell, rate, n_src, dt, \
+                                            n_steps, d)                                                   \
+                   : step_typed<GG, float>(c, (float *)N, (float *)F, x, T, n0, cell, rate, n_src, dt,    \
+                                           n_steps, d);
+    switch (G) {
+        DISPATCH(1)
+        DISPATCH(2)
+        DISPATCH(3)
+        DISPATCH(4)
+    }
+#undef DISPATCH
+    return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
+}
+
+extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *F0, const double *x0,
+                                    const double *T0, const double *n0, const int64_t *cell,
+                                    const double *rate, int32_t n_src, double dt, int32_t n_steps, void *gN,
+                                    void *gF, double *gx, double *gT, double *g_n0, double *g_rate) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (c->cfg.adjoint_max_steps < 1) return fail(c, EMMA_RT_EINVAL, "context was created without adjoint scratch");
+    if (n_steps < 1 || n_steps > c->cfg.adjoint_max_steps)
+        return fail(c, EMMA_RT_EINVAL, "n_steps must be in 1..%d", c->cfg.adjoint_max_steps);
+    if (!N0 || !F0 || !x0 || !T0 || !n0 || !gN || !gF || !gx || !gT || !g_n0)
+        return fail(c, EMMA_RT_EINVAL, "a field pointer is NULL");
+    if (n_src < 0 || n_src > EMMA_RT_MAX_SOURCES)
+        return fail(c, EMMA_RT_EINVAL, "n_src must be in 0..%d", EMMA_RT_MAX_SOURCES);
+    if (n_src > 0 && (!cell || !rate || !g_rate)) return fail(c, EMMA_RT_EINVAL, "source arrays are NULL");
+    if (!(dt > 0) || dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
+        return fail(c, EMMA_RT_EINVAL, "dt must be in (0, dx/(3 c_red)]");
+    c->err[0] = 0;
+    const int G = c->cfg.n_groups;
+    const bool f64 = c->cfg.precision == EMMA_RT_FP64;
+    AdjointCall call{c->stream, c->grid, group_consts(c->cfg), c->cfg, dt, n_steps,
+                     c->mask, c->sorted_cell, c->S, c->sorted_idx, n_src, c->Ns, c->Fs, c->cnt};
+#define ADISPATCH(GG)                                                                                        \
+    case GG: {                                                                                               \
+        int e = build_sources<GG>(c, cell, rate, n_src);                                                     \
+        if (e) return e;                                                                                     \
+        e = f64 ? adjoint_run<GG, double>(c->adj, call, (const double *)N0, (const double *)F0, x0, T0, n0, \
+                                          rate, (double *)gN, (double *)gF, gx, gT, g_n0, g_rate)            \
+                : adjoint_run<GG, float>(c->adj, call, (const float *)N0, (const float *)F0, x0, T0, n0,    \
+                                         rate, (float *)gN, (float *)gF, gx, gT, g_n0, g_rate);              \
+        if (e) return fail(c, EMMA_RT_EHIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError())); \
+        return EMMA_RT_OK;                                                                                   \
+    }
+    switch (G) {
+        ADISPATCH(1)
+        ADISPATCH(2)
+        ADISPATCH(3)
+        ADISPATCH(4)
+    }
+#undef ADISPATCH
+    return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
+}
+
+// ------------------------------------------------------------ profiling
+static const char *kKindNames[KID_COUNT] = {"src_table", "transport", "chemistry", "fused_step",
+                                            "diagnostics", "adj_chemistry", "adj_transport",
+                                            "adj_sources", "adj_forward"};
+
+extern "C" int emma_rt_profile_enable(emma_rt_ctx *c, int32_t enable) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (enable && !c->ev) {
+        c->ev = new std::vector<hipEvent_t>(2 * kEventPairs);
+        c->ev_kind = new std::vector<int>();
+        c->ev_kind->reserve(kEventPairs);
+        for (auto &e : *c->ev) HIP_TRY(c, hipEventCreate(&e));
+    }
+    if (!enable && c->ev) {
+        if (int e = prof_flush(c)) return e;
+    }
+    c->prof = enable ? 1 : 0;
+    return EMMA_RT_OK;
+}
+
+extern "C" int emma_rt_profile_read(emma_rt_ctx *c, emma_rt_kernel_time *out, int32_t max_out,
+                                    int32_t *n_out) {
+    if (!c || !n_out || (max_out > 0 && !out)) return fail(c, EMMA_RT_EINVAL, "bad arguments");
+    *n_out = 0;
+    if (c->ev) {
+        if (int e = prof_flush(c)) return e;
+    }
+    for (int k = 0; k < KID_COUNT; ++k) {
+        if (c->prof_n[k] == 0) continue;
+        if (*n_out < max_out) {
+            emma_rt_kernel_time &r = out[*n_out];
+            memset(&r, 0, sizeof(r));
+            strncpy(r.name, kKindNames[k], sizeof(r.name) - 1);
+            r.launches = c->prof_n[k];
+            r.total_ms = c->prof_ms[k];
+            (*n_out)++;
+        }
+        c->prof_n[k] = 0;
+        c->prof_ms[k] = 0.0;
+    }
+    return EMMA_RT_OK;
+}
+
+// ------------------------------------------------------- group constants
+// Hydrogen photo-ionisation cross-section, exact hydrogenic form
+// (Osterbrock & Ferland): s(E) = 6.30e-18 (E0/E)^4 exp(4 - 4 atan(q)/q) /
+// (1 - exp(-2 pi / q)), q = sqrt(E/E0 - 1), zero below E0 = 13.6 eV.
+static double h_cross_section(double E) {
+    const double E0 = 13.6;
+    if (E < E0) return 0.0;
+    const double r = E / E0;
+    const double q2 = r - 1.0;
+    if (q2 < 1e-12) return 6.30e-18;
+    const double q = sqrt(q2);
+    const double at = atan(q) / q;
+    return 6.30e-18 / (r * r * r * r) * exp(4.0 - 4.0 * at) / (-expm1(-2.0 * M_PI / q));
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+static void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w) {
+    t.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+        t[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+extern "C" int emma_rt_group_constants(double T_bb, const double *edges, int32_t G, double *sigN,
+                                       double *sigE, double *meanE, double *frac) {
+    if (G < 1 || G > EMMA_RT_MAX_GROUPS || !edges || !sigN || !sigE || !meanE || !frac || !(T_bb > 0))
+        return EMMA_RT_EINVAL;
+    for (int g = 0; g < G; ++g)
+        if (!(edges[g] >= 13.6) || !(edges[g + 1] > edges[g])) return EMMA_RT_EINVAL;
+    const double kT = kKB * T_bb / kEV;  // eV
+    std::vector<double> t, w;
+    const int order = 48, panels = 96;
+    gauss_legendre(order, t, w);
+    double tot = 0.0;
+    std::vector<double> num(G);
+    for (int g = 0; g < G; ++g) {
+        // photon spectrum per unit energy E^2 / (exp(E/kT) - 1), integrated in
+        // u = ln E (dE = E du) over equal panels
+        const double a = log(edges[g]), b = log(edges[g + 1]);
+        const double h = (b - a) / panels;
+        double In = 0, Is = 0, Ie = 0, Ise = 0;
+        for (int p = 0; p < panels; ++p) {
+            const double mid = a + (p + 0.5) * h;
+            for (int k = 0; k < order; ++k) {
+                const double E = exp(mid + 0.5 * h * t[k]);
+                const double wt = 0.5 * h * w[k] * E * E * E / expm1(E / kT);
+                const double s = h_cross_section(E);
+                In += wt;
+                Is += wt * s;
+                Ie += wt * E;
+                Ise += wt * s * E;
+            }
+        }
+        const double mE = Ie / In;
+        sigN[g] = Is / In;
+        sigE[g] = Ise / Ie;
+        meanE[g] = mE * kEV;
+        num[g] = In;
+        tot += In;
+    }
+    for (int g = 0; g < G; ++g) frac[g] = num[g] / tot;
+    return EMMA_RT_OK;
+}

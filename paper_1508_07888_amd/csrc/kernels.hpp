@@ -1,0 +1,359 @@
+// kernels.hpp -- HIP kernels of the radiation step (gfx950, wave64).
+//
+//   k_src_*        source table: stable rank sort of the point sources by host
+//                  cell, per-cell summed source density S_g = sum rate f_g / dx^3,
+//                  and a one-bit-per-cell mask so the chemistry reads one bit per
+//                  cell instead of a dense S field.
+//   k_transport    M1 transport of all groups, one thread per cell, reference form
+//                  (every face flux evaluated from both sides, like the paper's
+//                  gather; kept as the simple second implementation that the
+//                  fused kernel is tested against).
+//   k_chem         per-cell FP64 thermochemistry subcycle.
+//   k_fused        transport + chemistry in one pass (see fused.hpp).
+//   k_diag_*       deterministic reductions for the diagnostics.
+#pragma once
+
+#include "physics.hpp"
+
+namespace emma {
+
+struct Grid {
+    int nx, ny, nz;
+    int64_t V;  // nx * ny * nz
+};
+
+// Counters accumulated when diagnostics are requested.
+enum Counter {
+    CNT_LIMITER = 0,
+    CNT_NEG,
+    CNT_XCLAMP,
+    CNT_CAP,
+    CNT_SUB,
+    CNT_ATT,
+    CNT_NONFINITE,
+    CNT_BADSRC,
+    CNT_MAXSUB,   // max, via atomicMax
+    CNT_COUNT
+};
+
+// Kernel kinds for the per-kernel timing.
+enum KernelKind {
+    KID_SRC = 0,
+    KID_TRANSPORT,
+    KID_CHEM,
+    KID_FUSED,
+    KID_DIAG,
+    KID_ADJ_CHEM,
+    KID_ADJ_TRANSPORT,
+    KID_ADJ_SRC,
+    KID_ADJ_FWD,
+    KID_COUNT
+};
+
+__device__ inline int64_t wave_sum(int64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Adds v into cnt[idx] once per wave (all 64 lanes must call it).
+__device__ inline void wave_count(unsigned long long *cnt, int idx, int64_t v) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(cnt + idx, (unsigned long long)v);
+}
+
+// ------------------------------------------------------------------ sources
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Rank of each source in the order (cell, list position); cells outside the
+// grid get the key INT64_MAX so they sort last and are ignored.
+__global__ void k_src_rank(const int64_t *cell, int n, int64_t V, int64_t *sorted_cell,
+                           int32_t *sorted_idx, unsigned long long *cnt) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t INV = INT64_MAX;
+    int64_t ks = cell[s];
+    if (ks < 0 || ks >= V) {
+        ks = INV;
+        atomicAdd(cnt + CNT_BADSRC, 1ull);
+    }
+    int rank = 0;
+    for (int t = 0; t < n; ++t) {
+        int64_t kt = cell[t];
+        if (kt < 0 || kt >= V) kt = INV;
+        rank += (kt < ks) || (kt == ks && t < s);
+    }
+    sorted_cell[rank] = ks;
+    sorted_idx[rank] = s;
+}
+
+// At the head of every run of equal cells: S_g = sum over the run, in list
+// order, of rate * frac_g / dx^3, and the cell's bit in the mask.
+template <int G>
+__global__ void k_src_heads(const int64_t *sorted_cell, const int32_t *sorted_idx,
+                            const double *rate, int n, GroupConsts gc, double inv_vol_dx,
+                            double vol, double *S, uint32_t *mask) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t c = sorted_cell[r];
+    if (c == INT64_MAX) return;
+    if (r > 0 && sorted_cell[r - 1] == c) return;
+    double acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = 0.0;
+    for (int q = r; q < n && sorted_cell[q] == c; ++q) {
+        const double rt = rate[sorted_idx[q]];
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[g] += rt * gc.frac[g] / vol;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) S[(int64_t)r * G + g] = acc[g];
+    atomicOr(mask + (c >> 5), 1u << (c & 31));
+    (void)inv_vol_dx;
+}
+
+// First sorted position whose cell is >= c.
+__device__ inline int lower_bound_cell(const int64_t *sorted_cell, int n, int64_t c) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (sorted_cell[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int G>
+__device__ inline void source_of(int64_t i, const uint32_t *mask, const int64_t *sorted_cell,
+                                 const double *S, int n, double (&Sc)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) Sc[g] = 0.0;
+    if ((mask[i >> 5] >> (i & 31)) & 1u) {
+        const int r = lower_bound_cell(sorted_cell, n, i);
+#pragma unroll
+        for (int g = 0; g < G; ++g) Sc[g] = S[(int64_t)r * G + g];
+    }
+}
+
+struct SrcTable {
+    const uint32_t *mask;
+    const int64_t *sorted_cell;
+    const double *S;
+    int n;
+};
+
+// ---------------------------------------------------------------- transport
+// Reference transport: one thread per cell, all groups.  The update of cell i
+// is U* = U + (dt/dx) sum_d [flux(i-1/2) - flux(i+1/2)] with the flux of
+// eq. (e:glf), then N* >= 0 and |F*| <= c N*.
+template <typename R>
+__device__ inline void glf(R NL, const R FL[3], const R PL[6], R NR, const R FR[3], const R PR[6],
+                           int d, R c, R out[4]) {
+    // column d of the symmetric tensor: rows x, y, z
+    const int col[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    out[0] = R(0.5) * (FL[d] + FR[d]) - R(0.5) * c * (NR - NL);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        out[1 + k] = R(0.5) * c * c * (PL[col[k][d]] + PR[col[k][d]]) - R(0.5) * c * (FR[k] - FL[k]);
+}
+
+template <int G, typename R, bool DIAG>
+__global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, const R *__restrict__ F,
+                                                   R *__restrict__ Ns, R *__restrict__ Fs, Grid gr,
+                                                   R c, R lam, unsigned long long *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < gr.V;
+    int64_t nlim = 0, nneg = 0;
+    if (live) {
+        const int x = (int)(i % gr.nx);
+        const int y = (int)((i / gr.nx) % gr.ny);
+        const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
+        const int64_t V = gr.V;
+        int64_t nb[3][2];
+        {
+            const int xm = x == 0 ? gr.nx - 1 : x - 1, xp = x == gr.nx - 1 ? 0 : x + 1;
+            const int ym = y == 0 ? gr.ny - 1 : y - 1, yp = y == gr.ny - 1 ? 0 : y + 1;
+            const int zm = z == 0 ? gr.nz - 1 : z - 1, zp = z == gr.nz - 1 ? 0 : z + 1;
+            const int64_t row = (int64_t)gr.nx;
+            const int64_t pl = (int64_t)gr.nx * gr.ny;
+            const int64_t base = i - x;
+            nb[0][0] = base + xm;
+            nb[0][1] = base + xp;
+            nb[1][0] = i + (int64_t)(ym - y) * row;
+            nb[1][1] = i + (int64_t)(yp - y) * row;
+            nb[2][0] = i + (int64_t)(zm - z) * pl;
+            nb[2][1] = i + (int64_t)(zp - z) * pl;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const R *Ng = N + (int64_t)g * V;
+            const R *Fg = F + (int64_t)g * 3 * V;
+            const R Ni = Ng[i];
+            const R Fi[3] = {Fg[i], Fg[V + i], Fg[2 * V + i]};
+            R Pi[6];
+            m1_pressure(Ni, Fi[0], Fi[1], Fi[2], c, Pi);
+            R acc[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int64_t im = nb[d][0], ip = nb[d][1];
+                const R Nm = Ng[im], Np = Ng[ip];
+                const R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
+                const R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
+                R Pm[6], Pp[6];
+                m1_pressure(Nm, Fm[0], Fm[1], Fm[2], c, Pm);
+                m1_pressure(Np, Fp[0], Fp[1], Fp[2], c, Pp);
+                R lo[4], hi[4];
+                glf(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
+                glf(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[k] += lo[k] - hi[k];
+            }
+            R n = Ni + lam * acc[0];
+            R f[3] = {Fi[0] + lam * acc[1], Fi[1] + lam * acc[2], Fi[2] + lam * acc[3]};
+            if (n < R(0)) { n = R(0); nneg++; }
+            const R F2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+            if (F2 > R(0)) {
+                const R Fn = FastMath<R>::sqrt(F2);
+                if (Fn > c * n) {
+                    const R s = FastMath<R>::div(c * n, Fn);
+                    f[0] *= s; f[1] *= s; f[2] *= s;
+                    nlim++;
+                }
+            }
+            Ns[(int64_t)g * V + i] = n;
+            Fs[(int64_t)g * 3 * V + i] = f[0];
+            Fs[(int64_t)g * 3 * V + V + i] = f[1];
+            Fs[(int64_t)g * 3 * V + 2 * V + i] = f[2];
+        }
+    }
+    if (DIAG) {
+        wave_count(cnt, CNT_LIMITER, nlim);
+        wave_count(cnt, CNT_NEG, nneg);
+    }
+}
+
+// ---------------------------------------------------------------- chemistry
+// One thread per cell: reads the post-transport N*, F* (storage type S), the
+// gas state and the cell's source density; writes the end-of-step N, F, x, T.
+template <int G, typename S, bool DIAG>
+__global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S *__restrict__ Fs,
+                                              S *__restrict__ N, S *__restrict__ F,
+                                              double *__restrict__ x, double *__restrict__ T,
+                                              const double *__restrict__ n0, int64_t V,
+                                              SrcTable src, GroupConsts gc, ChemParams cp,
+                                              unsigned long long *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    ChemStats st{0, 0, 0, 0};
+    if (i < V) {
+        double Nc[G], Fc[G][3], Sc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            Nc[g] = (double)Ns[(int64_t)g * V + i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fc[g][k] = (double)Fs[((int64_t)g * 3 + k) * V + i];
+        }
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        double xc = x[i], Tc = T[i];
+        st = chem_cell<G>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            N[(int64_t)g * V + i] = (S)Nc[g];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + i] = (S)Fc[g][k];
+        }
+        x[i] = xc;
+        T[i] = Tc;
+    }
+    if (DIAG) {
+        wave_count(cnt, CNT_SUB, st.substeps);
+        wave_count(cnt, CNT_ATT, st.attempts);
+        wave_count(cnt, CNT_CAP, st.cap);
+        wave_count(cnt, CNT_XCLAMP, st.xclamp);
+        const int m = wave_max(st.substeps);
+        if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(cnt + CNT_MAXSUB, (unsigned long long)m);
+    }
+}
+
+// -------------------------------------------------------------- diagnostics
+// Per-block partial sums of N (per group) and x n0, plus the non-finite count;
+// the partials are summed in block order by k_diag_final (deterministic).
+template <int G, typename S>
+__global__ __launch_bounds__(256) void k_diag_partial(const S *N, const S *F, const double *x,
+                                                      const double *T, const double *n0, int64_t V,
+                                                      double *partial, unsigned long long *cnt) {
+    __shared__ double sh[G + 1][256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[G + 1];
+#pragma unroll
+    for (int q = 0; q < G + 1; ++q) v[q] = 0.0;
+    int64_t bad = 0;
+    if (i < V) {
+        bool fin = isfinite(x[i]) && isfinite(T[i]);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double n = (double)N[(int64_t)g * V + i];
+            v[g] = n;
+            fin = fin && isfinite(n);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fin = fin && isfinite((double)F[((int64_t)g * 3 + k) * V + i]);
+        }
+        v[G] = x[i] * n0[i];
+        bad = fin ? 0 : 1;
+    }
+    wave_count(cnt, CNT_NONFINITE, bad);
+#pragma unroll
+    for (int q = 0; q < G + 1; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < G + 1; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < G + 1; ++q) partial[(int64_t)blockIdx.x * (G + 1) + q] = sh[q][0];
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_diag_final(const double *partial, int nblk, double *out) {
+    __shared__ double sh[G + 1][256];
+    double v[G + 1];
+#pragma unroll
+    for (int q = 0; q < G + 1; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+#pragma unroll
+        for (int q = 0; q < G + 1; ++q) v[q] += partial[(int64_t)b * (G + 1) + q];
+    }
+#pragma unroll
+    for (int q = 0; q < G + 1; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < G + 1; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < G + 1; ++q) out[q] = sh[q][0];
+    }
+}
+
+}  // namespace emma

@@ -1,0 +1,157 @@
+"""PyTorch-facing wrapper of the radiation step library.
+
+PyTorch provides device memory and the stream; the C ABI of libemma_rt.so does
+all the work.  Fields are torch tensors on the context's device:
+    N  [G, nz, ny, nx]      float32 (mixed) or float64 (fp64)   photons cm^-3
+    F  [G, 3, nz, ny, nx]   same dtype as N                      photons cm^-2 s^-1
+    x  [nz, ny, nx]         float64   ionised fraction x_HII
+    T  [nz, ny, nx]         float64   K
+    n0 [nz, ny, nx]         float64   total hydrogen density n_H, cm^-3
+    src_cell [n_src] int64 (flat cell index), src_rate [n_src] float64 (photons/s)
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+
+C_LIGHT = 2.99792458e10
+
+
+def group_constants(T_bb, edges_eV):
+    """Black-body group constants computed by the library (host quadrature)."""
+    return _lib.emma_rt_group_constants(T_bb, list(edges_eV))
+
+
+class EmmaRT:
+    """One radiation context: a fixed grid, group set and precision.
+
+    Calls run on the torch stream that is current on ``device`` when the
+    context is created.
+    """
+
+    def __init__(self, shape, n_groups, dx, c_red, precision="mixed", groups=None, T_bb=1e5,
+                 edges_eV=None, otsa=True, isothermal=False, max_substeps=100000,
+                 adjoint_max_steps=0, device="cuda:0"):
+        nz, ny, nx = shape
+        self.shape = (nz, ny, nx)
+        self.G = int(n_groups)
+        self.dx = float(dx)
+        self.c_red = float(c_red)
+        self.precision = precision
+        if precision not in ("mixed", "fp64"):
+            raise ValueError("precision must be 'mixed' or 'fp64'")
+        self.dtype = torch.float32 if precision == "mixed" else torch.float64
+        self.device = torch.device(device)
+        if groups is None:
+            if edges_eV is None:
+                raise ValueError("give either groups or edges_eV")
+            groups = group_constants(T_bb, edges_eV)
+        self.groups = {k: [float(v) for v in groups[k]][: self.G]
+                       for k in ("sigma_N", "sigma_E", "mean_E", "frac")}
+        cfg = _lib.emma_rt_config()
+        cfg.nx, cfg.ny, cfg.nz, cfg.n_groups = nx, ny, nz, self.G
+        cfg.dx, cfg.c_red = self.dx, self.c_red
+        cfg.precision = _lib.EMMA_RT_MIXED if precision == "mixed" else _lib.EMMA_RT_FP64
+        cfg.otsa, cfg.isothermal = int(bool(otsa)), int(bool(isothermal))
+        cfg.max_substeps = int(max_substeps)
+        cfg.adjoint_max_steps = int(adjoint_max_steps)
+        for g in range(self.G):
+            cfg.sigma_N[g] = self.groups["sigma_N"][g]
+            cfg.sigma_E[g] = self.groups["sigma_E"][g]
+            cfg.mean_E[g] = self.groups["mean_E"][g]
+            cfg.src_frac[g] = self.groups["frac"][g]
+        self.cfg = cfg
+        self.adjoint_max_steps = int(adjoint_max_steps)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self._ctx = _lib.emma_rt_init(cfg, self.stream.cuda_stream)
+
+    # ---------------------------------------------------------------- helpers
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.emma_rt_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t, name, dtype, shape):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, context is on {self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr()
+
+    def _fields(self, N, F, x, T, n0):
+        G, s = self.G, self.shape
+        return (self._check(N, "N", self.dtype, (G,) + s),
+                self._check(F, "F", self.dtype, (G, 3) + s),
+                self._check(x, "x", torch.float64, s),
+                self._check(T, "T", torch.float64, s),
+                self._check(n0, "n0", torch.float64, s))
+
+    def _sources(self, src_cell, src_rate):
+        n = int(src_cell.numel())
+        if n == 0:
+            return 0, 0, 0
+        pc = self._check(src_cell, "src_cell", torch.int64, (n,))
+        pr = self._check(src_rate, "src_rate", torch.float64, (n,))
+        return n, pc, pr
+
+    def new_state(self, x0=1.2e-3, T0=100.0):
+        G, s = self.G, self.shape
+        N = torch.zeros((G,) + s, dtype=self.dtype, device=self.device)
+        F = torch.zeros((G, 3) + s, dtype=self.dtype, device=self.device)
+        x = torch.full(s, x0, dtype=torch.float64, device=self.device)
+        T = torch.full(s, T0, dtype=torch.float64, device=self.device)
+        return N, F, x, T
+
+    def profile(self, enable=True):
+        """Turn per-kernel event timing on or off."""
+        _lib.emma_rt_profile_enable(self._ctx, enable)
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms)} since the last read (waits)."""
+        return _lib.emma_rt_profile_read(self._ctx)
+
+    def max_dt(self):
+        return self.dx / (3.0 * self.c_red)
+
+    # ------------------------------------------------------------------ calls
+    def step(self, N, F, x, T, n0, src_cell, src_rate, dt, n_steps=1, diag=False,
+             raise_on_status=True):
+        """Advance the state in place; returns the diagnostics dict if asked."""
+        pN, pF, px, pT, pn = self._fields(N, F, x, T, n0)
+        n, pc, pr = self._sources(src_cell, src_rate)
+        d = _lib.emma_rt_diag() if diag else None
+        rc = _lib.emma_rt_step(self._ctx, pN, pF, px, pT, pn, pc, pr, n, dt, n_steps, d)
+        if rc != _lib.EMMA_RT_OK and raise_on_status:
+            raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))
+        if diag:
+            out = d.as_dict(self.G)
+            out["status"] = rc
+            return out
+        return rc
+
+    def step_adjoint(self, N0, F0, x0, T0, n0, src_cell, src_rate, dt, n_steps, gN, gF, gx, gT,
+                     g_n0, g_rate):
+        """In place: (gN, gF, gx, gT) from dL/d(end state) to dL/d(start state);
+        g_n0 and g_rate are accumulated."""
+        pN, pF, px, pT, pn = self._fields(N0, F0, x0, T0, n0)
+        qN, qF, qx, qT, qn = self._fields(gN, gF, gx, gT, g_n0)
+        n, pc, pr = self._sources(src_cell, src_rate)
+        qr = self._check(g_rate, "g_rate", torch.float64, (n,)) if n else 0
+        rc = _lib.emma_rt_step_adjoint(self._ctx, pN, pF, px, pT, pn, pc, pr, n, dt, n_steps,
+                                       qN, qF, qx, qT, qn, qr)
+        if rc != _lib.EMMA_RT_OK:
+            raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))

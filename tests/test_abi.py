@@ -1,0 +1,95 @@
+"""The C ABI on the host: the library loads, exports every entry point that
+include/emma_rt.h declares, rejects bad configurations before touching the
+GPU, and its own group-constant quadrature agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import emma_inputs as E
+import oracle
+from paper_1508_07888_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "emma_rt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(emma_rt_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = _declared()
+    assert set(names) == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_layouts_match_header():
+    # offsets the header implies (int32 x4, double x2, int32 x6, double[4] x4)
+    assert ctypes.sizeof(_lib.emma_rt_config) == 16 + 16 + 24 + 4 * 32
+    assert _lib.emma_rt_config.sigma_N.offset == 56
+    assert ctypes.sizeof(_lib.emma_rt_diag) == 32 + 8 + 16 + 8 + 40
+
+
+def _cfg(**kw):
+    c = _lib.emma_rt_config()
+    c.nx = c.ny = c.nz = 8
+    c.n_groups = 1
+    c.dx, c.c_red = 1e20, 3e9
+    c.precision = _lib.EMMA_RT_FP64
+    c.otsa, c.max_substeps = 1, 100
+    c.sigma_N[0] = c.sigma_E[0] = 1e-18
+    c.mean_E[0] = 3e-11
+    c.src_frac[0] = 1.0
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nx=0), "grid"), (dict(n_groups=5), "n_groups"), (dict(n_groups=0), "n_groups"),
+    (dict(dx=0.0), "dx"), (dict(c_red=4e10), "c_red"), (dict(precision=7), "precision"),
+    (dict(max_substeps=0), "max_substeps"), (dict(adjoint_max_steps=-1), "adjoint"),
+])
+def test_init_rejects_bad_config(kw, msg):
+    L = _lib.load()
+    ctx = ctypes.c_void_p()
+    rc = L.emma_rt_init(ctypes.byref(ctx), ctypes.byref(_cfg(**kw)), None)
+    assert rc == _lib.EMMA_RT_EINVAL
+    assert not ctx
+    assert msg in _lib.emma_rt_last_error(None)
+
+
+def test_null_arguments_are_rejected():
+    L = _lib.load()
+    assert L.emma_rt_init(None, ctypes.byref(_cfg()), None) == _lib.EMMA_RT_EINVAL
+    assert L.emma_rt_step(None, *([None] * 7), 0, 1.0, 1, None) == _lib.EMMA_RT_EINVAL
+    L.emma_rt_free(None)
+
+
+def test_scratch_bytes():
+    c = _cfg(nx=256, ny=256, nz=256, n_groups=3, precision=_lib.EMMA_RT_MIXED)
+    b = _lib.emma_rt_scratch_bytes(c)
+    V = 256 ** 3
+    assert b >= 12 * V * 4 and b < 12 * V * 4 * 1.1
+    assert _lib.emma_rt_scratch_bytes(_cfg(nx=0)) == -1
+
+
+@pytest.mark.parametrize("G", [1, 2, 3, 4])
+def test_library_group_constants_match_oracle(G):
+    a = _lib.emma_rt_group_constants(E.T_BB, E.EDGES[G])
+    b = oracle.group_constants(E.T_BB, E.EDGES[G])
+    for k in ("sigma_N", "sigma_E", "mean_E", "frac"):
+        assert np.max(np.abs(np.array(a[k]) / b[k] - 1)) < 1e-10, k
+
+
+def test_group_constants_reject_bad_edges():
+    with pytest.raises(_lib.EmmaError):
+        _lib.emma_rt_group_constants(1e5, [13.6, 10.0])
+    with pytest.raises(_lib.EmmaError):
+        _lib.emma_rt_group_constants(1e5, [13.6, 20, 30, 40, 50, 60])
