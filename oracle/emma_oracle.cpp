@@ -36,6 +36,7 @@
  *   R10 accept when |e' - e| <= 0.1 e.  At most MAX_HALVINGS halvings per
  *       substep; after max_substeps accepted substeps one last substep of
  *       length dt_rem is taken unconditionally.  Both count as cap hits.
+ *       A cell whose energy is not positive and finite is left unchanged.
  *   R11 e = 3/2 (1+x) n0 k_B T (gamma = 5/3).
  *   R12 rates, cooling and cross-section are the fits written out below.
  *   R13 x is clamped to [0, 1] after its update; N* >= 0 after transport;
@@ -266,6 +267,9 @@ int chem_cell(const Params &p, R *N, R (*F)[3], R &x, R &T, R n0, const R *S,
     R rem = R(p.dt);
     int nsub = 0, attempts = 0, cap = 0, xclamp = 0;
     while (rem > R(0.0)) {
+        /* R10: a cell whose energy is not a positive finite number (invalid
+         * input) is left as it stands for the rest of the step. */
+        if (!p.isothermal && !(val(e) > 0.0 && val(e) < HUGE_VAL)) break;
         bool last = nsub >= p.max_substeps;          /* R10 */
         R Tp = p.isothermal ? T : e / (1.5 * (1.0 + x) * n0 * K_B);
         Rates<R> r = rates_at(Tp);
