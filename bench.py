@@ -59,13 +59,13 @@ def traffic_from_profiles(kernel, workload, precision):
     return d.get("hbm_bytes_per_launch")
 
 
-def run_gpu(w, precision, steps, warmup):
+def run_gpu(w, precision, steps, warmup, path="fused"):
     import torch
     from paper_1508_07888_amd import EmmaRT
     dev = "cuda:0"
     G = w["G"]
     rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"],
-                edges_eV=w["edges"], device=dev)
+                edges_eV=w["edges"], path=path, device=dev)
     fdt = rt.dtype
     N0 = torch.tensor(w["N"], dtype=fdt, device=dev)
     F0 = torch.tensor(w["F"], dtype=fdt, device=dev)
@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--path", default="fused", choices=["fused", "split", "reference"],
+                    help="kernel path (all compute the same step; fused is the product path)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the radiation step is built and timed on a "
@@ -134,8 +136,8 @@ def main():
     import emma_inputs as E
     w = E.make_workload(args.workload, n=args.n)
     G = w["G"]
-    mixed = run_gpu(w, "mixed", args.steps, args.warmup)
-    fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup)
+    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.path)
+    fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup, args.path)
 
     kern = mixed["kernels"]
     dom = max((k for k in kern if k != "src_table"), key=lambda k: kern[k][1])
@@ -163,7 +165,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": w["shape"][0], "groups": G,
                    "sources": int(w["src_cell"].size), "c_red_over_c": w["c_red"] / E.C_LIGHT,
-                   "precision": "mixed"},
+                   "precision": "mixed", "path": args.path},
         "roofline": roofline,
         "group_cell_updates_per_s": mixed["value"] * G,
         "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()},

@@ -50,6 +50,7 @@ typedef enum {
 } emma_rt_status;
 
 typedef enum { EMMA_RT_FP64 = 0, EMMA_RT_MIXED = 1 } emma_rt_precision;
+typedef enum { EMMA_RT_PATH_FUSED = 0, EMMA_RT_PATH_SPLIT = 1, EMMA_RT_PATH_REFERENCE = 2 } emma_rt_path;
 
 #define EMMA_RT_MAX_GROUPS 4
 #define EMMA_RT_MAX_SOURCES 65536
@@ -68,7 +69,10 @@ typedef struct {
                                    guard takes one last substep of the remainder */
     int32_t adjoint_max_steps;  /* K: longest segment emma_rt_step_adjoint accepts;
                                    0 = no adjoint scratch */
-    int32_t reserved;
+    int32_t path;               /* kernels of the step: EMMA_RT_PATH_FUSED (default),
+                                   _SPLIT (tiled transport, then chemistry) or
+                                   _REFERENCE (one-cell-per-thread transport, then
+                                   chemistry); all compute the same step */
     /* Per-group constants (Sec. 2.2.3-2.2.4, eq. e:siggroup and the sigma_E and
        <E> definitions): number- and energy-weighted cross-sections (cm^2), mean
        photon energy (erg) and fraction of a source's photons in the group. */

@@ -5,6 +5,6 @@ as hand-written HIP kernels for gfx950 behind a C ABI (include/emma_rt.h),
 with a thin ctypes/PyTorch binding.
 """
 from . import _lib
-from .rt import EmmaRT, group_constants
+from .rt import EmmaRT, RTStep, group_constants
 
-__all__ = ["EmmaRT", "group_constants", "_lib"]
+__all__ = ["EmmaRT", "RTStep", "group_constants", "_lib"]

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESUBSTEP",
 
 EMMA_RT_FP64 = 0
 EMMA_RT_MIXED = 1
+PATHS = {"fused": 0, "split": 1, "reference": 2}
 
 EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_adjoint", "emma_rt_free",
            "emma_rt_last_error", "emma_rt_group_constants", "emma_rt_scratch_bytes",
@@ -35,7 +36,7 @@ class emma_rt_config(ctypes.Structure):
         ("dx", ctypes.c_double), ("c_red", ctypes.c_double),
         ("precision", ctypes.c_int32), ("otsa", ctypes.c_int32), ("isothermal", ctypes.c_int32),
         ("max_substeps", ctypes.c_int32), ("adjoint_max_steps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("path", ctypes.c_int32),
         ("sigma_N", ctypes.c_double * MAX_GROUPS), ("sigma_E", ctypes.c_double * MAX_GROUPS),
         ("mean_E", ctypes.c_double * MAX_GROUPS), ("src_frac", ctypes.c_double * MAX_GROUPS),
     ]

@@ -1,4 +1,17 @@
 // adjoint.hpp -- reverse-mode derivative of the radiation step.
+//
+// The step is U -> transport (eq. e:uprt with the flux of eq. e:glf, then the
+// floor N >= 0 and the limiter |F| <= c N) -> per-cell chemistry subcycle
+// (Sec. 2.2.4).  Its exact derivative along the branches the forward run takes
+// (dtau0 = rem or |e/(H - Lambda)|, the number of 10 % halvings, clamps) is
+// applied in reverse:
+//   k_chem_adj       per cell: replays the cell's substeps with the forward's
+//                    own substep() (identical decisions), then runs them
+//                    backwards; also reverses the floor and limiter.  Adds
+//                    dL/dn0 and dL/dS (per source cell).
+//   k_transport_adj  per cell, gather form (no atomics): the transpose of the
+//                    radius-1 stencil with the closure Jacobian dP/d(N, F).
+//   k_src_grad       dL/d(source rate) = sum_g frac_g / dx^3 dL/dS_g(host cell).
 #pragma once
 
 #include "kernels.hpp"
@@ -7,42 +20,481 @@
 namespace emma {
 
 struct AdjointScratch {
-    void *tape;
-    int64_t bytes;
+    void *tape;      // [K][state]: N, F (storage type), x, T (double)
+    double *gU;      // [4 G][V]: dL/d(pre-limiter transport output)
+    double *gS;      // [EMMA_RT_MAX_SOURCES][G]: dL/dS per sorted source position
+    int64_t tape_bytes_per_step;
 };
 
-struct AdjointCall {
-    hipStream_t stream;
-    Grid grid;
-    GroupConsts gc;
-    emma_rt_config cfg;
-    double dt;
-    int n_steps;
-    const uint32_t *mask;
-    const int64_t *sorted_cell;
-    const double *S;
-    const int32_t *sorted_idx;
-    int n_src;
-    void *Ns, *Fs;
-    unsigned long long *cnt;
-};
+inline int64_t adjoint_state_bytes(const emma_rt_config &cfg) {
+    const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    const int64_t e = cfg.precision == EMMA_RT_FP64 ? 8 : 4;
+    return V * (4 * cfg.n_groups * e + 16);
+}
 
-inline int64_t adjoint_scratch_bytes(const emma_rt_config &) { return 0; }
-inline int adjoint_alloc(AdjointScratch &a, const emma_rt_config &) {
+inline int64_t adjoint_scratch_bytes(const emma_rt_config &cfg) {
+    if (cfg.adjoint_max_steps < 1) return 0;
+    const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    return cfg.adjoint_max_steps * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * 8 +
+           (int64_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8;
+}
+
+inline int adjoint_alloc(AdjointScratch &a, const emma_rt_config &cfg) {
     a.tape = nullptr;
-    a.bytes = 0;
+    a.gU = nullptr;
+    a.gS = nullptr;
+    a.tape_bytes_per_step = adjoint_state_bytes(cfg);
+    if (cfg.adjoint_max_steps < 1) return 0;
+    const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    if (hipMalloc(&a.tape, (size_t)(cfg.adjoint_max_steps * a.tape_bytes_per_step)) != hipSuccess) return -1;
+    if (hipMalloc((void **)&a.gU, (size_t)(4 * cfg.n_groups * V * 8)) != hipSuccess) return -1;
+    if (hipMalloc((void **)&a.gS, (size_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8) != hipSuccess) return -1;
     return 0;
 }
+
 inline void adjoint_release(AdjointScratch &a) {
     if (a.tape) (void)hipFree(a.tape);
+    if (a.gU) (void)hipFree(a.gU);
+    if (a.gS) (void)hipFree(a.gS);
     a.tape = nullptr;
+    a.gU = nullptr;
+    a.gS = nullptr;
+}
+
+// ------------------------------------------------------- chemistry adjoint
+struct RateAdj {
+    double alpha, dalpha, beta, crec, cci, cce, cff;
+};
+
+// Lambda(n0, x) = (crec + cff) ne^2 + (cci + cce) ne nh, ne = x n0, nh = (1-x) n0:
+// adds lam * dLambda/d(.) to the rate adjoints, x and n0.
+__host__ __device__ __forceinline__ void cooling_adj(const RateSet &r, double n0, double x, double lam, RateAdj &ar,
+                                            double &ax, double &an0) {
+    const double ne = x * n0, nh = (1.0 - x) * n0;
+    ar.crec += lam * ne * ne;
+    ar.cff += lam * ne * ne;
+    ar.cci += lam * ne * nh;
+    ar.cce += lam * ne * nh;
+    const double ane = lam * (2.0 * (r.crec + r.cff) * ne + (r.cci + r.cce) * nh);
+    const double anh = lam * (r.cci + r.cce) * ne;
+    ax += (ane - anh) * n0;
+    an0 += ane * x + anh * (1.0 - x);
+}
+
+// Reverse of one chemistry substep that started from (N, x, e, rem) and took
+// the decisions in info.  On entry aN, ax, ae, arem hold dL/d(end state of the
+// substep); on exit dL/d(start state).  aF[g] = dL/d(factor applied to F_g)
+// from outside (the F path).  Adds to an0, aS and aT (the temperature input,
+// isothermal mode only).
+template <int G, bool FAST>
+__host__ __device__ inline void substep_adj(const GroupConsts &gc, const ChemParams &p, double n0, double eunit,
+                                   const double (&S)[G], const double (&N)[G], double x, double e,
+                                   double rem, const SubInfo &info, const double (&aFinv)[G], double (&aN)[G],
+                                   double &ax, double &ae, double &arem, double &an0, double (&aS)[G],
+                                   double &aT) {
+    const double c = p.c;
+    const bool otsa = FAST ? true : (p.otsa != 0);
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    const double Tp = info.Tp;
+    const RateSet r = FAST ? rates_at<true>(Tp) : rates_at(Tp, otsa);
+    // dtau of the accepted attempt
+    double dtau0 = rem;
+    if (info.branch) dtau0 = fabs(e * recip_fp64(info.D));
+    const double dtau = ldexp(dtau0, -info.h);
+    // forward intermediates of the accepted attempt
+    const double y0 = 1.0 - x;
+    double kap[G], inv[G], Nn[G], rec[G], gam = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        kap[g] = c * gc.sigN[g] * y0 * n0;
+        rec[g] = (g == 0) ? r.dalpha * x * x * n0 * n0 : 0.0;
+        inv[g] = recip_fp64(1.0 + dtau * kap[g]);
+        Nn[g] = (N[g] + (S[g] + rec[g]) * dtau) * inv[g];
+        gam += c * gc.sigN[g] * Nn[g];
+    }
+    const double num = r.alpha * x * x * n0 * dtau + y0;
+    const double denx = 1.0 + dtau * (r.beta * x * n0 + gam);
+    const double rdx = recip_fp64(denx);
+    const double xn = info.xclamp ? (info.xclamp > 0 ? 1.0 : 0.0) : 1.0 - num * rdx;
+
+    RateAdj ar{0, 0, 0, 0, 0, 0, 0};
+    double adt = 0.0, axs = 0.0, aes = 0.0;
+    double aNn[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) aNn[g] = aN[g];
+    // rem' = rem - dtau
+    const double arems = arem;
+    adt -= arem;
+    double axn = ax;
+    if (!iso) {
+        // e' = e + dtau (H' - Lambda'),  H' = c (1 - x') n0 sum_g SigE_g N'_g
+        aes += ae;
+        double hs = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) hs += gc.SigE[g] * Nn[g];
+        const double Hn = c * (1.0 - xn) * n0 * hs;
+        const double Ln = cooling(r, n0, xn);
+        adt += ae * (Hn - Ln);
+        const double aH = ae * dtau;
+        axn -= aH * c * n0 * hs;
+        an0 += aH * c * (1.0 - xn) * hs;
+#pragma unroll
+        for (int g = 0; g < G; ++g) aNn[g] += aH * c * (1.0 - xn) * n0 * gc.SigE[g];
+        cooling_adj(r, n0, xn, -ae * dtau, ar, axn, an0);
+    }
+    // x' = 1 - num / denx (unless clamped)
+    if (!info.xclamp) {
+        const double anum = -axn * rdx;
+        const double aden = axn * num * rdx * rdx;
+        ar.alpha += anum * x * x * n0 * dtau;
+        axs += anum * (2.0 * r.alpha * x * n0 * dtau - 1.0);
+        an0 += anum * r.alpha * x * x * dtau;
+        adt += anum * r.alpha * x * x * n0;
+        adt += aden * (r.beta * x * n0 + gam);
+        ar.beta += aden * dtau * x * n0;
+        axs += aden * dtau * r.beta * n0;
+        an0 += aden * dtau * r.beta * x;
+        const double agam = aden * dtau;
+#pragma unroll
+        for (int g = 0; g < G; ++g) aNn[g] += agam * c * gc.sigN[g];
+    }
+    // N'_g = (N_g + (S_g + rec_g) dtau) inv_g,  inv_g = 1 / (1 + dtau kap_g)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        aN[g] = aNn[g] * inv[g];
+        aS[g] += aNn[g] * dtau * inv[g];
+        const double arec = aNn[g] * dtau * inv[g];
+        adt += aNn[g] * (S[g] + rec[g]) * inv[g];
+        const double ainv = aNn[g] * (N[g] + (S[g] + rec[g]) * dtau) + aFinv[g];
+        const double aden = -ainv * inv[g] * inv[g];
+        adt += aden * kap[g];
+        const double akap = aden * dtau;
+        axs -= akap * c * gc.sigN[g] * n0;
+        an0 += akap * c * gc.sigN[g] * y0;
+        if (g == 0) {
+            ar.dalpha += arec * x * x * n0 * n0;
+            axs += arec * 2.0 * r.dalpha * x * n0 * n0;
+            an0 += arec * 2.0 * r.dalpha * x * x * n0;
+        }
+    }
+    // dtau = dtau0 / 2^h; dtau0 = rem or |e / D|, D = H - Lambda at the start
+    const double adt0 = ldexp(adt, -info.h);
+    double aremo = arems;
+    if (!info.branch) {
+        aremo += adt0;
+    } else {
+        const double D = info.D;
+        const double sg = D < 0.0 ? -1.0 : 1.0;
+        const double rD = recip_fp64(D);
+        aes += adt0 * sg * rD;
+        const double aD = -adt0 * e * sg * rD * rD;
+        double hs0 = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) hs0 += gc.SigE[g] * N[g];
+        axs -= aD * c * n0 * hs0;
+        an0 += aD * c * (1.0 - x) * hs0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) aN[g] += aD * c * (1.0 - x) * n0 * gc.SigE[g];
+        cooling_adj(r, n0, x, -aD, ar, axs, an0);
+    }
+    // rates at Tp
+    const RateSet dr = (FAST || otsa) ? rates_dT<true>(Tp, r) : rates_dT<false>(Tp, r);
+    const double aTp = ar.alpha * dr.alpha + ar.dalpha * dr.dalpha + ar.beta * dr.beta + ar.crec * dr.crec +
+                       ar.cci * dr.cci + ar.cce * dr.cce + ar.cff * dr.cff;
+    if (iso) {
+        aT += aTp;
+    } else {
+        // Tp = e / (eunit (1 + x)), eunit = 1.5 k_B n0
+        aes += aTp / (eunit * (1.0 + x));
+        axs -= aTp * Tp / (1.0 + x);
+        an0 -= aTp * Tp / n0;
+    }
+    ax = axs;
+    ae = aes;
+    arem = aremo;
+}
+
+// Reverse of chem_cell: inputs (N, F, x, T) of the subcycle and dL/d(outputs)
+// -> dL/d(inputs), dL/dn0, dL/dS.  The substep sequence is recomputed with
+// substep() from the cell's start for each substep in turn (cost quadratic in
+// the substep count of the cell, which is 1 or 2 for almost every cell).
+template <int G, bool FAST>
+__host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemParams &p, const double (&N0)[G],
+                                     const double (&F0)[G][3], double x0, double T0, double n0,
+                                     const double (&S)[G], const double (&aNo)[G], const double (&aFo)[G][3],
+                                     double axo, double aTo, double (&aN)[G], double (&aF)[G][3], double &ax,
+                                     double &aT, double &an0, double (&aS)[G]) {
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    const double eunit = 1.5 * n0 * kKB;
+    const double e0 = eunit * (1.0 + x0) * T0;
+    // forward pass: substep count, end state, product of the F factors
+    double N[G], Pf[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) { N[g] = N0[g]; Pf[g] = 1.0; }
+    double x = x0, e = e0, rem = p.dt;
+    ChemStats st{0, 0, 0, 0};
+    int K = 0;
+    while (rem > 0.0) {
+        const bool last = K >= p.max_substeps;
+        double inv[G];
+        if (!substep<G, FAST>(gc, p, last, n0, eunit, T0, S, N, x, e, rem, inv, st, nullptr)) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g) Pf[g] *= inv[g];
+        K++;
+        if (last || iso) break;
+    }
+    // F_out = F_in prod_k inv_k: dL/dinv_k (through F) = Phi_g / inv_k
+    double Phi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        Phi[g] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            aF[g][k] = aFo[g][k] * Pf[g];
+            Phi[g] += aFo[g][k] * F0[g][k] * Pf[g];
+        }
+        aN[g] = aNo[g];
+        aS[g] = 0.0;
+    }
+    ax = axo;
+    aT = 0.0;
+    an0 = 0.0;
+    double ae = 0.0, arem = 0.0;
+    if (!iso) {
+        // T_out = e / (eunit (1 + x))
+        const double Tf = e / (eunit * (1.0 + x));
+        ae += aTo / (eunit * (1.0 + x));
+        ax -= aTo * Tf / (1.0 + x);
+        an0 -= aTo * Tf / n0;
+    } else {
+        aT += aTo;
+    }
+    for (int k = K - 1; k >= 0; --k) {
+        double Ns[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) Ns[g] = N0[g];
+        double xs = x0, es = e0, rs = p.dt;
+        ChemStats st2{0, 0, 0, 0};
+        double inv[G];
+        for (int j = 0; j < k; ++j)
+            substep<G, FAST>(gc, p, j >= p.max_substeps, n0, eunit, T0, S, Ns, xs, es, rs, inv, st2, nullptr);
+        // decisions of substep k from its start state
+        double Nk[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) Nk[g] = Ns[g];
+        double xk = xs, ek = es, rk = rs;
+        SubInfo info;
+        substep<G, FAST>(gc, p, k >= p.max_substeps, n0, eunit, T0, S, Nk, xk, ek, rk, inv, st2, &info);
+        double aFinv[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) aFinv[g] = Phi[g] / inv[g];
+        substep_adj<G, FAST>(gc, p, n0, eunit, S, Ns, xs, es, rs, info, aFinv, aN, ax, ae, arem, an0, aS, aT);
+    }
+    if (!iso) {
+        // e0 = eunit (1 + x0) T0
+        aT += ae * eunit * (1.0 + x0);
+        ax += ae * eunit * T0;
+        an0 += ae * 1.5 * kKB * (1.0 + x0) * T0;
+    }
+}
+
+// Floor and limiter after the stencil: N* = max(N~, 0); F* = F~ c N*/|F~|
+// when |F~| > c N*.  Forward in place (a = the post values).
+__host__ __device__ __forceinline__ bool floor_limit(double &n, double &fx, double &fy, double &fz, double c, bool &floored) {
+    floored = n < 0.0;
+    if (floored) n = 0.0;
+    const double F2 = fx * fx + fy * fy + fz * fz;
+    const double cn = c * n;
+    if (F2 > cn * cn) {
+        const double s = cn / sqrt(F2);
+        fx *= s; fy *= s; fz *= s;
+        return true;
+    }
+    return false;
+}
+
+// Reverse of floor_limit given the PRE values (n, f) and dL/d(post values).
+__host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, double fy, double fz, double c, double &an,
+                                                double &afx, double &afy, double &afz) {
+    const bool floored = n < 0.0;
+    const double np = floored ? 0.0 : n;
+    const double F2 = fx * fx + fy * fy + fz * fz;
+    const double cn = c * np;
+    if (F2 > cn * cn) {
+        const double Fn = sqrt(F2);
+        const double ux = fx / Fn, uy = fy / Fn, uz = fz / Fn;
+        const double ud = ux * afx + uy * afy + uz * afz;
+        an += c * ud;
+        const double s = cn / Fn;
+        afx = s * (afx - ux * ud);
+        afy = s * (afy - uy * ud);
+        afz = s * (afz - uz * ud);
+    }
+    if (floored) an = 0.0;
+}
+
+template <int G, typename S, bool FAST>
+__global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
+                                                  const double *__restrict__ xs, const double *__restrict__ Ts,
+                                                  const double *__restrict__ n0, int64_t V, SrcTable src,
+                                                  GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
+                                                  const S *__restrict__ gF, double *__restrict__ gx,
+                                                  double *__restrict__ gT, double *__restrict__ g_n0,
+                                                  double *__restrict__ gS, double *__restrict__ gU) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const double c = cp.c;
+    double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], aNo[G], aFo[G][3], Sc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        Npre[g] = (double)Ut[(int64_t)g * V + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fpre[g][k] = (double)Ft[((int64_t)g * 3 + k) * V + i];
+        Nst[g] = Npre[g];
+        Fst[g][0] = Fpre[g][0];
+        Fst[g][1] = Fpre[g][1];
+        Fst[g][2] = Fpre[g][2];
+        bool fl;
+        floor_limit(Nst[g], Fst[g][0], Fst[g][1], Fst[g][2], c, fl);
+        aNo[g] = (double)gN[(int64_t)g * V + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) aFo[g][k] = (double)gF[((int64_t)g * 3 + k) * V + i];
+    }
+    source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+    double aN[G], aF[G][3], aS[G], ax, aT, an0;
+    chem_cell_adj<G, FAST>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i], aN, aF, ax, aT, an0,
+                           aS);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, aN[g], aF[g][0], aF[g][1], aF[g][2]);
+        gU[(int64_t)(4 * g) * V + i] = aN[g];
+        gU[(int64_t)(4 * g + 1) * V + i] = aF[g][0];
+        gU[(int64_t)(4 * g + 2) * V + i] = aF[g][1];
+        gU[(int64_t)(4 * g + 3) * V + i] = aF[g][2];
+    }
+    gx[i] = ax;
+    gT[i] = aT;
+    g_n0[i] += an0;
+    if ((src.mask[i >> 5] >> (i & 31)) & 1u) {
+        const int r = lower_bound_cell(src.sorted_cell, src.n, i);
+#pragma unroll
+        for (int g = 0; g < G; ++g) gS[(int64_t)r * G + g] += aS[g];
+    }
+}
+
+// ------------------------------------------------------- transport adjoint
+// Closure derivatives of P = a I + bq F F^T (a = (1-chi)/2 N, bq = (3chi-1)/2 N/|F|^2,
+// chi(q), q = |F|^2/(c N)^2 clipped at 1):  da/dN, da/dF = ga F, bq,
+// dbq/dN, dbq/dF = gb F.
+struct ClosureJac {
+    double aN, ga, bq, bqN, gb;
+};
+
+__host__ __device__ __forceinline__ ClosureJac closure_jac(double N, double Fx, double Fy, double Fz, double c) {
+    ClosureJac j{1.0 / 3.0, 0.0, 0.0, 0.0, 0.0};
+    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+    if (!(N > 0.0) || !(F2 > 0.0)) return j;  // P = N/3 I: only dP/dN = I/3
+    const double icn = 1.0 / (c * N);
+    double q = F2 * icn * icn;
+    double dchi = 0.0;
+    if (q >= 1.0) {
+        q = 1.0;
+    } else {
+        const double s = sqrt(4.0 - 3.0 * q);
+        const double den = 5.0 + 2.0 * s;
+        dchi = (4.0 * den + 3.0 * (3.0 + 4.0 * q) / s) / (den * den);
+    }
+    const double s = sqrt(4.0 - 3.0 * q);
+    const double chi = (3.0 + 4.0 * q) / (5.0 + 2.0 * s);
+    const double B = 0.5 * (3.0 * chi - 1.0) * N;
+    j.aN = 0.5 * (1.0 - chi) + dchi * q;
+    j.ga = -dchi * icn * icn * N;  // -chi' / (c^2 N)
+    j.bq = B / F2;
+    j.bqN = (0.5 * (3.0 * chi - 1.0) - 3.0 * dchi * q) / F2;
+    j.gb = 3.0 * dchi * icn * icn * N / F2 - 2.0 * B / (F2 * F2);
+    return j;
 }
 
 template <int G, typename S>
-inline int adjoint_run(AdjointScratch &, const AdjointCall &, const S *, const S *, const double *,
-                       const double *, const double *, const double *, S *, S *, double *, double *,
-                       double *, double *) {
-    return -1;
+__global__ __launch_bounds__(256) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
+                                                       const double *__restrict__ gU, S *__restrict__ gN,
+                                                       S *__restrict__ gF, Grid gr, double c, double lam) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= gr.V) return;
+    const int64_t V = gr.V;
+    const int x = (int)(i % gr.nx);
+    const int y = (int)((i / gr.nx) % gr.ny);
+    const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
+    int64_t nb[3][2];
+    {
+        const int xm = x == 0 ? gr.nx - 1 : x - 1, xp = x == gr.nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? gr.ny - 1 : y - 1, yp = y == gr.ny - 1 ? 0 : y + 1;
+        const int zm = z == 0 ? gr.nz - 1 : z - 1, zp = z == gr.nz - 1 ? 0 : z + 1;
+        const int64_t row = gr.nx, pl = (int64_t)gr.nx * gr.ny;
+        nb[0][0] = i - x + xm;
+        nb[0][1] = i - x + xp;
+        nb[1][0] = i + (int64_t)(ym - y) * row;
+        nb[1][1] = i + (int64_t)(yp - y) * row;
+        nb[2][0] = i + (int64_t)(zm - z) * pl;
+        nb[2][1] = i + (int64_t)(zp - z) * pl;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double n = (double)N[(int64_t)g * V + i];
+        const double Fv[3] = {(double)F[((int64_t)g * 3) * V + i], (double)F[((int64_t)g * 3 + 1) * V + i],
+                              (double)F[((int64_t)g * 3 + 2) * V + i]};
+        const ClosureJac J = closure_jac(n, Fv[0], Fv[1], Fv[2], c);
+        const double *gUg = gU + (int64_t)(4 * g) * V;
+        double out[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = (1.0 - 3.0 * c * lam) * gUg[(int64_t)q * V + i];
+        const double cc = c * c;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double vp[4], vm[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                vp[q] = gUg[(int64_t)q * V + nb[d][1]];
+                vm[q] = gUg[(int64_t)q * V + nb[d][0]];
+                out[q] += 0.5 * lam * c * (vp[q] + vm[q]);
+            }
+            // (lam/2) M_d(U)^T (v+ - v-),  M_d = dFt_d/dU,  Ft_d = (F_d, c^2 P_.d)
+            const double vN = vp[0] - vm[0];
+            const double w[3] = {vp[1] - vm[1], vp[2] - vm[2], vp[3] - vm[3]};
+            const double wF = w[0] * Fv[0] + w[1] * Fv[1] + w[2] * Fv[2];
+            const double mN = cc * (J.aN * w[d] + J.bqN * wF * Fv[d]);
+            out[0] += 0.5 * lam * mN;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double mk = cc * (J.ga * Fv[k] * w[d] + J.gb * Fv[k] * wF * Fv[d] + J.bq * w[k] * Fv[d]);
+                if (k == d) mk += vN + cc * J.bq * wF;
+                out[1 + k] += 0.5 * lam * mk;
+            }
+        }
+        gN[(int64_t)g * V + i] = (S)out[0];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gF[((int64_t)g * 3 + k) * V + i] = (S)out[1 + k];
+    }
+}
+
+// dL/d(rate of source s) += sum_g frac_g / dx^3 dL/dS_g(host cell of s).
+template <int G>
+__global__ void k_src_grad(const int64_t *cell, int n, int64_t V, const int64_t *sorted_cell, const double *gS,
+                           GroupConsts gc, double vol, double *g_rate) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t cs = cell[s];
+    if (cs < 0 || cs >= V) return;
+    const int r = lower_bound_cell(sorted_cell, n, cs);
+    double acc = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc += gc.frac[g] / vol * gS[(int64_t)r * G + g];
+    g_rate[s] += acc;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 }  // namespace emma

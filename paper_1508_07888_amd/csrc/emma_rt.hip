@@ -33,12 +33,11 @@ struct emma_rt_ctx {
     int64_t *sorted_cell;  // [EMMA_RT_MAX_SOURCES]
     int32_t *sorted_idx;
     double *S;             // [EMMA_RT_MAX_SOURCES][G]
-    unsigned long long *cnt;     // [CNT_COUNT]
+    unsigned long long *cnt;     // [kCntSlots][CNT_COUNT]
     double *partial;             // [nblk][G+1]
     int diag_blocks;
     double *dsum;                // [G+1]
     AdjointScratch adj;
-    int use_fused;               // 1: fused transport+chemistry kernel
     // kernel timing (emma_rt_profile_enable)
     int prof;
     std::vector<hipEvent_t> *ev;     // pool, pairs (start, stop)
@@ -129,6 +128,10 @@ static const char *config_error(const emma_rt_config *cfg) {
     if (cfg->precision != EMMA_RT_FP64 && cfg->precision != EMMA_RT_MIXED) return "bad precision";
     if (cfg->max_substeps < 1) return "max_substeps must be >= 1";
     if (cfg->adjoint_max_steps < 0) return "adjoint_max_steps must be >= 0";
+    if (cfg->path < EMMA_RT_PATH_FUSED || cfg->path > EMMA_RT_PATH_REFERENCE) return "bad path";
+    if (cfg->path != EMMA_RT_PATH_REFERENCE &&
+        !tiled_supported(Grid{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz}))
+        return "grid too large for the tiled kernels (V * 8 bytes >= 4 GiB): use the reference path";
     for (int g = 0; g < cfg->n_groups; ++g) {
         if (!(cfg->sigma_N[g] >= 0) || !(cfg->sigma_E[g] >= 0) || !(cfg->mean_E[g] >= 0) ||
             !(cfg->src_frac[g] >= 0))
@@ -149,7 +152,7 @@ extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
     int64_t b = field_bytes(cfg);                          // Ns + Fs
     b += ((V + 31) / 32) * 4;                              // mask
     b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
-    b += CNT_COUNT * 8;
+    b += kCntSlots * CNT_COUNT * 8;
     b += ((V + 255) / 256) * (cfg->n_groups + 1) * 8 + (cfg->n_groups + 1) * 8;
     b += adjoint_scratch_bytes(*cfg);
     return b;
@@ -190,7 +193,6 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
     c->grid.nz = cfg->nz;
     c->grid.V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     c->elem = cfg->precision == EMMA_RT_FP64 ? 8 : 4;
-    c->use_fused = fused_supported(c->grid) ? 1 : 0;
     (void)hipGetDevice(&c->device);
     const int64_t V = c->grid.V;
     const int G = cfg->n_groups;
@@ -203,7 +205,7 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
         {(void **)&c->sorted_cell, (size_t)EMMA_RT_MAX_SOURCES * 8},
         {(void **)&c->sorted_idx, (size_t)EMMA_RT_MAX_SOURCES * 4},
         {(void **)&c->S, (size_t)EMMA_RT_MAX_SOURCES * G * 8},
-        {(void **)&c->cnt, (size_t)CNT_COUNT * 8},
+        {(void **)&c->cnt, (size_t)kCntSlots * CNT_COUNT * 8},
         {(void **)&c->partial, (size_t)c->diag_blocks * (G + 1) * 8},
         {(void **)&c->dsum, (size_t)(G + 1) * 8},
     };
@@ -272,7 +274,7 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
     S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
     const S cr = (S)c->cfg.c_red;
     const S lam = (S)(dt / c->cfg.dx);
-    if (c->use_fused) {
+    if (c->cfg.path == EMMA_RT_PATH_FUSED) {
         // ping-pong: even steps read the caller's buffers, odd steps the scratch
         for (int s = 0; s < n_steps; ++s) {
             const bool even = (s & 1) == 0;
@@ -294,7 +296,11 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
         return EMMA_RT_OK;
     }
     for (int s = 0; s < n_steps; ++s) {
-        {
+        if (c->cfg.path == EMMA_RT_PATH_SPLIT) {
+            Timed t(c, KID_TRANSPORT);
+            launch_tiled<G, S, DIAG, false>(c->stream, N, F, Ns, Fs, x, T, n0, gr, src, gc, cp,
+                                            dt / c->cfg.dx, c->cnt);
+        } else {
             Timed t(c, KID_TRANSPORT);
             hipLaunchKernelGGL((k_transport<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, N, F, Ns,
                                Fs, gr, cr, lam, c->cnt);
@@ -302,8 +308,12 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
         if (int e = check_launch(c, "k_transport")) return e;
         {
             Timed t(c, KID_CHEM);
-            hipLaunchKernelGGL((k_chem<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F, x,
-                               T, n0, V, src, gc, cp, c->cnt);
+            if (cp.otsa && !cp.isothermal)
+                hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N,
+                                   F, x, T, n0, V, src, gc, cp, c->cnt);
+            else
+                hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs,
+                                   N, F, x, T, n0, V, src, gc, cp, c->cnt);
         }
         if (int e = check_launch(c, "k_chem")) return e;
     }
@@ -319,11 +329,18 @@ static int diag_finish(emma_rt_ctx *c, const S *N, const S *F, const double *x, 
     hipLaunchKernelGGL((k_diag_final<G>), dim3(1), dim3(256), 0, c->stream, c->partial, c->diag_blocks,
                        c->dsum);
     if (int e = check_launch(c, "k_diag_final")) return e;
-    unsigned long long cnt[CNT_COUNT];
+    unsigned long long slots[kCntSlots * CNT_COUNT], cnt[CNT_COUNT];
     double sums[EMMA_RT_MAX_GROUPS + 1];
-    HIP_TRY(c, hipMemcpyAsync(cnt, c->cnt, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(slots, c->cnt, sizeof(slots), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(sums, c->dsum, (G + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < CNT_COUNT; ++k) {
+        cnt[k] = 0;
+        for (int j = 0; j < kCntSlots; ++j) {
+            const unsigned long long v = slots[j * CNT_COUNT + k];
+            cnt[k] = k == CNT_MAXSUB ? (v > cnt[k] ? v : cnt[k]) : cnt[k] + v;
+        }
+    }
     const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
     memset(d, 0, sizeof(*d));
     for (int g = 0; g < G; ++g) d->photons[g] = sums[g] * vol;
@@ -349,7 +366,8 @@ static int step_typed(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
                       const int64_t *cell, const double *rate, int n_src, double dt, int n_steps,
                       emma_rt_diag *d) {
     if (d) {
-        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, c->stream, c->cnt, (int)CNT_COUNT, 0ull);
+        hipLaunchKernelGGL(k_fill_u64, dim3((kCntSlots * CNT_COUNT + 255) / 256), dim3(256), 0, c->stream,
+                           c->cnt, (int)(kCntSlots * CNT_COUNT), 0ull);
         if (int e = check_launch(c, "k_fill_u64")) return e;
     }
     if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
@@ -394,6 +412,82 @@ extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double 
     return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
 }
 
+// ----------------------------------------------------------------- adjoint
+template <int G, typename S>
+static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double *x0, const double *T0,
+                         const double *n0, const int64_t *cell, const double *rate, int n_src, double dt,
+                         int n_steps, S *gN, S *gF, double *gx, double *gT, double *g_n0, double *g_rate) {
+    const Grid gr = c->grid;
+    const int64_t V = gr.V;
+    const int tb = 256;
+    const unsigned nblk = (unsigned)((V + tb - 1) / tb);
+    const GroupConsts gc = group_consts(c->cfg);
+    ChemParams cp;
+    cp.c = c->cfg.c_red;
+    cp.dt = dt;
+    cp.otsa = c->cfg.otsa;
+    cp.isothermal = c->cfg.isothermal;
+    cp.max_substeps = c->cfg.max_substeps;
+    const bool fast = cp.otsa && !cp.isothermal;
+    const double lam = dt / c->cfg.dx;
+    const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
+    // tape: state at the start of every step of the segment
+    const int64_t step_bytes = c->adj.tape_bytes_per_step;
+    auto tN = [&](int s) { return (S *)((char *)c->adj.tape + s * step_bytes); };
+    auto tF = [&](int s) { return tN(s) + (int64_t)G * V; };
+    auto tx = [&](int s) { return (double *)(tF(s) + (int64_t)3 * G * V); };
+    auto tT = [&](int s) { return tx(s) + V; };
+    if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
+    const size_t nb = (size_t)G * V * sizeof(S), fb = 3 * nb, db = (size_t)V * 8;
+    HIP_TRY(c, hipMemcpyAsync(tN(0), N0, nb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(tF(0), F0, fb, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(tx(0), x0, db, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(tT(0), T0, db, hipMemcpyDeviceToDevice, c->stream));
+    for (int s = 0; s + 1 < n_steps; ++s) {
+        HIP_TRY(c, hipMemcpyAsync(tN(s + 1), tN(s), (size_t)step_bytes, hipMemcpyDeviceToDevice, c->stream));
+        Timed t(c, KID_ADJ_FWD);
+        if (int e = run_steps<G, S, false>(c, tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1), n0, n_src, dt, 1))
+            return e;
+    }
+    SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
+    if (n_src > 0) {
+        hipLaunchKernelGGL(k_fill_f64, dim3((n_src * G + tb - 1) / tb), dim3(tb), 0, c->stream, c->adj.gS,
+                           (int64_t)n_src * G, 0.0);
+        if (int e = check_launch(c, "k_fill_f64")) return e;
+    }
+    S *Ut = (S *)c->Ns, *Ft = (S *)c->Fs;
+    for (int s = n_steps - 1; s >= 0; --s) {
+        {
+            Timed t(c, KID_ADJ_FWD);
+            hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
+                               Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt);
+        }
+        if (int e = check_launch(c, "k_transport (adjoint recompute)")) return e;
+        {
+            Timed t(c, KID_ADJ_CHEM);
+            if (fast)
+                hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU);
+            else
+                hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU);
+        }
+        if (int e = check_launch(c, "k_chem_adj")) return e;
+        {
+            Timed t(c, KID_ADJ_TRANSPORT);
+            hipLaunchKernelGGL((k_transport_adj<G, S>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
+                               c->adj.gU, gN, gF, gr, c->cfg.c_red, lam);
+        }
+        if (int e = check_launch(c, "k_transport_adj")) return e;
+    }
+    if (n_src > 0) {
+        Timed t(c, KID_ADJ_SRC);
+        hipLaunchKernelGGL(k_src_grad<G>, dim3((n_src + tb - 1) / tb), dim3(tb), 0, c->stream, cell, n_src, V,
+                           c->sorted_cell, c->adj.gS, gc, vol, g_rate);
+    }
+    return check_launch(c, "k_src_grad");
+}
+
 extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *F0, const double *x0,
                                     const double *T0, const double *n0, const int64_t *cell,
                                     const double *rate, int32_t n_src, double dt, int32_t n_steps, void *gN,
@@ -409,22 +503,20 @@ extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *
     if (n_src > 0 && (!cell || !rate || !g_rate)) return fail(c, EMMA_RT_EINVAL, "source arrays are NULL");
     if (!(dt > 0) || dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
         return fail(c, EMMA_RT_EINVAL, "dt must be in (0, dx/(3 c_red)]");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
     c->err[0] = 0;
     const int G = c->cfg.n_groups;
     const bool f64 = c->cfg.precision == EMMA_RT_FP64;
-    AdjointCall call{c->stream, c->grid, group_consts(c->cfg), c->cfg, dt, n_steps,
-                     c->mask, c->sorted_cell, c->S, c->sorted_idx, n_src, c->Ns, c->Fs, c->cnt};
 #define ADISPATCH(GG)                                                                                        \
-    case GG: {                                                                                               \
-        int e = build_sources<GG>(c, cell, rate, n_src);                                                     \
-        if (e) return e;                                                                                     \
-        e = f64 ? adjoint_run<GG, double>(c->adj, call, (const double *)N0, (const double *)F0, x0, T0, n0, \
-                                          rate, (double *)gN, (double *)gF, gx, gT, g_n0, g_rate)            \
-                : adjoint_run<GG, float>(c->adj, call, (const float *)N0, (const float *)F0, x0, T0, n0,    \
-                                         rate, (float *)gN, (float *)gF, gx, gT, g_n0, g_rate);              \
-        if (e) return fail(c, EMMA_RT_EHIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError())); \
-        return EMMA_RT_OK;                                                                                   \
-    }
+    case GG:                                                                                                 \
+        return f64 ? adjoint_typed<GG, double>(c, (const double *)N0, (const double *)F0, x0, T0, n0, cell,  \
+                                               rate, n_src, dt, n_steps, (double *)gN, (double *)gF, gx, gT, \
+                                               g_n0, g_rate)                                                 \
+                   : adjoint_typed<GG, float>(c, (const float *)N0, (const float *)F0, x0, T0, n0, cell,     \
+                                              rate, n_src, dt, n_steps, (float *)gN, (float *)gF, gx, gT,    \
+                                              g_n0, g_rate);
     switch (G) {
         ADISPATCH(1)
         ADISPATCH(2)

@@ -61,10 +61,23 @@ __device__ inline int wave_max(int v) {
     return v;
 }
 
-// Adds v into cnt[idx] once per wave (all 64 lanes must call it).
+// Counters live in kCntSlots copies so that concurrent waves do not all hit
+// one address; slot = block index mod kCntSlots, summed on the host.
+constexpr int kCntSlots = 64;
+
+__device__ inline unsigned long long *cnt_slot(unsigned long long *cnt) {
+    return cnt + (blockIdx.x & (kCntSlots - 1)) * CNT_COUNT;
+}
+
+// Adds v into counter idx once per wave (all 64 lanes must call it).
 __device__ inline void wave_count(unsigned long long *cnt, int idx, int64_t v) {
     v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(cnt + idx, (unsigned long long)v);
+    if ((threadIdx.x & 63) == 0 && v != 0) atomicAdd(cnt_slot(cnt) + idx, (unsigned long long)v);
+}
+
+__device__ inline void wave_count_max(unsigned long long *cnt, int idx, int v) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(cnt_slot(cnt) + idx, (unsigned long long)v);
 }
 
 // ------------------------------------------------------------------ sources
@@ -88,7 +101,7 @@ __global__ void k_src_rank(const int64_t *cell, int n, int64_t V, int64_t *sorte
     int64_t ks = cell[s];
     if (ks < 0 || ks >= V) {
         ks = INV;
-        atomicAdd(cnt + CNT_BADSRC, 1ull);
+        atomicAdd(cnt_slot(cnt) + CNT_BADSRC, 1ull);
     }
     int rank = 0;
     for (int t = 0; t < n; ++t) {
@@ -170,7 +183,9 @@ __device__ inline void glf(R NL, const R FL[3], const R PL[6], R NR, const R FR[
         out[1 + k] = R(0.5) * c * c * (PL[col[k][d]] + PR[col[k][d]]) - R(0.5) * c * (FR[k] - FL[k]);
 }
 
-template <int G, typename R, bool DIAG>
+// NOLIMIT = true skips the floor and limiter (the adjoint needs the values
+// before them).
+template <int G, typename R, bool DIAG, bool NOLIMIT = false>
 __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, const R *__restrict__ F,
                                                    R *__restrict__ Ns, R *__restrict__ Fs, Grid gr,
                                                    R c, R lam, unsigned long long *cnt) {
@@ -223,9 +238,9 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
             }
             R n = Ni + lam * acc[0];
             R f[3] = {Fi[0] + lam * acc[1], Fi[1] + lam * acc[2], Fi[2] + lam * acc[3]};
-            if (n < R(0)) { n = R(0); nneg++; }
+            if (!NOLIMIT && n < R(0)) { n = R(0); nneg++; }
             const R F2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
-            if (F2 > R(0)) {
+            if (!NOLIMIT && F2 > R(0)) {
                 const R Fn = FastMath<R>::sqrt(F2);
                 if (Fn > c * n) {
                     const R s = FastMath<R>::div(c * n, Fn);
@@ -248,7 +263,7 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
 // ---------------------------------------------------------------- chemistry
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
 // gas state and the cell's source density; writes the end-of-step N, F, x, T.
-template <int G, typename S, bool DIAG>
+template <int G, typename S, bool DIAG, bool FAST>
 __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S *__restrict__ Fs,
                                               S *__restrict__ N, S *__restrict__ F,
                                               double *__restrict__ x, double *__restrict__ T,
@@ -267,7 +282,7 @@ __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S 
         }
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
         double xc = x[i], Tc = T[i];
-        st = chem_cell<G>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc);
+        st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             N[(int64_t)g * V + i] = (S)Nc[g];
@@ -282,8 +297,7 @@ __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S 
         wave_count(cnt, CNT_ATT, st.attempts);
         wave_count(cnt, CNT_CAP, st.cap);
         wave_count(cnt, CNT_XCLAMP, st.xclamp);
-        const int m = wave_max(st.substeps);
-        if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(cnt + CNT_MAXSUB, (unsigned long long)m);
+        wave_count_max(cnt, CNT_MAXSUB, st.substeps);
     }
 }
 

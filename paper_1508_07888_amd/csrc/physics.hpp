@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fastmath.hpp"
+
 namespace emma {
 
 constexpr double kC = 2.99792458e10;        // cm/s
@@ -52,32 +54,28 @@ template <> struct FastMath<double> {
     __device__ static inline double div(double a, double b) { return a / b; }
 };
 
+// With n = F/|F| and f^2 = |F|^2 / (c N)^2, P = a I + (b/|F|^2) F F^T where
+// a = (1 - chi)/2 N and b = (3 chi - 1)/2 N; chi depends on f^2 only, so no
+// square root of |F|^2 and no normalisation of F is needed.
 template <typename R>
-__device__ inline void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) {
+__device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) {
     using M = FastMath<R>;
     const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    const R Fn = F2 > R(0) ? M::sqrt(F2) : R(0);
-    R f = R(0);
-    if (N > R(0)) {
-        f = M::div(Fn, c * N);
-        f = f < R(1) ? f : R(1);
+    R a = N * R(1.0 / 3.0), bq = R(0);  // chi = 1/3 when N <= 0 or F = 0
+    if (N > R(0) && F2 > R(0)) {
+        const R icn = M::rcp(c * N);
+        R f2 = (F2 * icn) * icn;
+        f2 = f2 < R(1) ? f2 : R(1);
+        const R chi = (R(3) + R(4) * f2) * M::rcp(R(5) + R(2) * M::sqrt(R(4) - R(3) * f2));
+        a = R(0.5) * (R(1) - chi) * N;
+        bq = R(0.5) * (R(3) * chi - R(1)) * N * M::rcp(F2);
     }
-    const R f2 = f * f;
-    const R chi = M::div(R(3) + R(4) * f2, R(5) + R(2) * M::sqrt(R(4) - R(3) * f2));
-    const R a = R(0.5) * (R(1) - chi) * N;        // isotropic part
-    const R b = R(0.5) * (R(3) * chi - R(1)) * N; // along n
-    R nx = R(0), ny = R(0), nz = R(0);
-    if (Fn > R(0)) {
-        nx = M::div(Fx, Fn);
-        ny = M::div(Fy, Fn);
-        nz = M::div(Fz, Fn);
-    }
-    P[0] = a + b * nx * nx;
-    P[1] = b * nx * ny;
-    P[2] = b * nx * nz;
-    P[3] = a + b * ny * ny;
-    P[4] = b * ny * nz;
-    P[5] = a + b * nz * nz;
+    P[0] = a + bq * Fx * Fx;
+    P[1] = bq * Fx * Fy;
+    P[2] = bq * Fx * Fz;
+    P[3] = a + bq * Fy * Fy;
+    P[4] = bq * Fy * Fz;
+    P[5] = a + bq * Fz * Fz;
 }
 
 // ------------------------------------------------------------------- rates
@@ -91,27 +89,84 @@ struct RateSet {
     double cff;     // bremsstrahlung, erg cm^3/s
 };
 
-__device__ inline RateSet rates_at(double T, bool otsa) {
+// All rate fits share the form A T^t lam^a / (1 + (lam/b)^c)^d with
+// lam = 2 T_HI / T.  They are evaluated in the log domain from one
+// L = ln(lam): A T^t exp(a L - d ln(1 + exp(c (L - ln b)))), i.e. two exp and
+// one log per fit instead of four pow (same value to a few ulp; ln(1 + u)
+// only needs a small ABSOLUTE error here since it is scaled by d inside exp).
+__host__ __device__ __forceinline__ double hg_fit(double L, double a, double lnb, double c, double d) {
+    return a * L - d * log_fp64(1.0 + exp_fp64(c * (L - lnb)));
+}
+
+template <bool OTSA>
+__host__ __device__ __forceinline__ RateSet rates_at(double T) {
     RateSet r;
-    const double lam = 2.0 * kTHI / T;
-    const double aB = 2.753e-14 * pow(lam, 1.500) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
-    double aA = 0.0;
-    if (!otsa) aA = 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
-    r.alpha = otsa ? aB : aA;
-    r.dalpha = otsa ? 0.0 : aA - aB;
-    r.beta = 21.11 * pow(T, -1.5) * exp(-lam / 2.0) * pow(lam, -1.089) /
-             pow(1.0 + pow(lam / 0.354, 0.874), 1.101);
-    r.crec = otsa ? 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam / 2.250, 0.376), 3.720)
-                  : 1.778e-29 * T * pow(lam, 1.965) / pow(1.0 + pow(lam / 0.541, 0.502), 2.697);
+    const double invT = recip_fp64(T);
+    const double lam = 2.0 * kTHI * invT;
+    const double L = log_fp64(lam);
+    const double lnT = 12.662275226919286 - L;  // ln(2 T_HI) - L
+    if (OTSA) {
+        r.alpha = 2.753e-14 * exp_fp64(hg_fit(L, 1.500, 1.007957920399979, 0.407, 2.242));  // ln 2.740
+        r.dalpha = 0.0;
+        r.crec = 3.435e-30 * T * exp_fp64(hg_fit(L, 1.970, 0.8109302162163288, 0.376, 3.720));  // ln 2.250
+    } else {
+        const double aA = 1.269e-13 * exp_fp64(hg_fit(L, 1.503, -0.6500876910994983, 0.470, 1.923));  // ln 0.522
+        const double aB = 2.753e-14 * exp_fp64(hg_fit(L, 1.500, 1.007957920399979, 0.407, 2.242));
+        r.alpha = aA;
+        r.dalpha = aA - aB;
+        r.crec = 1.778e-29 * T * exp_fp64(hg_fit(L, 1.965, -0.6143360001356555, 0.502, 2.697));  // ln 0.541
+    }
+    // 21.11 T^-1.5 exp(-lam/2) lam^-1.089 / (1 + (lam/0.354)^0.874)^1.101
+    r.beta = 21.11 * exp_fp64(-1.5 * lnT - 0.5 * lam + hg_fit(L, -1.089, -1.0384583658483626, 0.874, 1.101));  // ln 0.354
     r.cci = kKB * kTHI * r.beta;
-    r.cce = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
-    r.cff = 1.42e-27 * 1.3 * sqrt(T);
+    const double sT = sqrt(T);
+    // 118348 K: collisional excitation temperature; sqrt(T / 1e5) = sT / 316.2...
+    r.cce = 7.5e-19 * exp_fp64(-118348.0 * invT) * recip_fp64(1.0 + sT * 0.003162277660168379);
+    r.cff = 1.42e-27 * 1.3 * sT;
     return r;
+}
+
+__host__ __device__ __forceinline__ RateSet rates_at(double T, bool otsa) {
+    return otsa ? rates_at<true>(T) : rates_at<false>(T);
+}
+
+// d(fit exponent)/dL of hg_fit.
+__host__ __device__ __forceinline__ double hg_slope(double L, double a, double lnb, double c, double d) {
+    const double u = exp_fp64(c * (L - lnb));
+    return a - d * c * u / (1.0 + u);
+}
+
+// Temperature derivatives of every coefficient of rates_at<OTSA>(T), given
+// its values r (dL/dT = -1/T).
+template <bool OTSA>
+__host__ __device__ inline RateSet rates_dT(double T, const RateSet &r) {
+    RateSet d;
+    const double invT = recip_fp64(T);
+    const double lam = 2.0 * kTHI * invT;
+    const double L = log_fp64(lam);
+    if (OTSA) {
+        d.alpha = -r.alpha * hg_slope(L, 1.500, 1.007957920399979, 0.407, 2.242) * invT;
+        d.dalpha = 0.0;
+        d.crec = r.crec * (1.0 - hg_slope(L, 1.970, 0.8109302162163288, 0.376, 3.720)) * invT;
+    } else {
+        const double aA = r.alpha, aB = r.alpha - r.dalpha;
+        const double daA = -aA * hg_slope(L, 1.503, -0.6500876910994983, 0.470, 1.923) * invT;
+        const double daB = -aB * hg_slope(L, 1.500, 1.007957920399979, 0.407, 2.242) * invT;
+        d.alpha = daA;
+        d.dalpha = daA - daB;
+        d.crec = r.crec * (1.0 - hg_slope(L, 1.965, -0.6143360001356555, 0.502, 2.697)) * invT;
+    }
+    d.beta = r.beta * (-1.5 + 0.5 * lam - hg_slope(L, -1.089, -1.0384583658483626, 0.874, 1.101)) * invT;
+    d.cci = kKB * kTHI * d.beta;
+    const double sT = sqrt(T), k = 0.003162277660168379;
+    d.cce = r.cce * (118348.0 * invT * invT - 0.5 * k / sT / (1.0 + k * sT));
+    d.cff = 0.5 * r.cff * invT;
+    return d;
 }
 
 // Cooling rate Lambda(n0, x, T) (erg cm^-3 s^-1) with n_e = n_p = x n0 and
 // n_HI = (1 - x) n0.
-__device__ inline double cooling(const RateSet &r, double n0, double x) {
+__host__ __device__ __forceinline__ double cooling(const RateSet &r, double n0, double x) {
     const double ne = x * n0;
     const double nHI = (1.0 - x) * n0;
     return (r.crec + r.cff) * ne * ne + (r.cci + r.cce) * ne * nHI;
@@ -134,74 +189,116 @@ struct ChemStats {
     int substeps, attempts, cap, xclamp;
 };
 
+// Decisions taken by one accepted substep (what the adjoint replays).
+struct SubInfo {
+    double Tp;     // temperature the rates were evaluated at
+    double D;      // H - Lambda at the start of the substep
+    int branch;    // 0: dtau0 = dt_rem, 1: dtau0 = |e / D|
+    int h;         // number of halvings of dtau0
+    int xclamp;    // 0: none, -1: x' clamped to 0, +1: x' clamped to 1
+};
+
+// One substep of the Sec. 2.2.4 sequence from the start state (N, x, e, rem):
+// dtau0 = min(rem, |e / (H - Lambda)|) (rem on the last, guarded substep),
+// halved until |e' - e| <= 0.1 e; returns false (state untouched) for an
+// invalid energy.  On return (N, x, e, rem) is the new state and inv[g] the
+// factor applied to F_g.  FAST = true compiles the default mode (on-the-spot,
+// energy evolved) with those flags as constants; FAST = false reads them from p.
+template <int G, bool FAST>
+__host__ __device__ __forceinline__ bool substep(const GroupConsts &gc, const ChemParams &p, bool last, double n0,
+                                        double eunit, double Tfix, const double (&S)[G], double (&N)[G],
+                                        double &x, double &e, double &rem, double (&inv)[G], ChemStats &st,
+                                        SubInfo *info) {
+    const double c = p.c;
+    const bool otsa = FAST ? true : (p.otsa != 0);
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    if (!iso && !(e > 0.0 && e < HUGE_VAL)) return false;  // invalid input: leave the cell
+    const double Tp = iso ? Tfix : e * recip_fp64(eunit * (1.0 + x));
+    const RateSet r = FAST ? rates_at<true>(Tp) : rates_at(Tp, otsa);
+    double dtau = rem, D = 0.0;
+    int branch = 0;
+    if (!iso && !last) {
+        double h = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) h += gc.SigE[g] * N[g];
+        const double H = c * (1.0 - x) * n0 * h;
+        const double L = cooling(r, n0, x);
+        D = H - L;
+        if (H != L) {
+            const double q = fabs(e * recip_fp64(D));
+            if (q < rem) { dtau = q; branch = 1; }
+        }
+    }
+    double Nn[G], xn, en;
+    int halvings = 0, xcl = 0;
+    for (;;) {
+        st.attempts++;
+        const double y0 = 1.0 - x;
+        double gam = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const double kap = c * gc.sigN[g] * y0 * n0;
+            const double rec = (g == 0) ? r.dalpha * x * x * n0 * n0 : 0.0;
+            inv[g] = recip_fp64(1.0 + dtau * kap);
+            Nn[g] = (N[g] + (S[g] + rec) * dtau) * inv[g];
+            gam += c * gc.sigN[g] * Nn[g];
+        }
+        xn = 1.0 - (r.alpha * x * x * n0 * dtau + y0) * recip_fp64(1.0 + dtau * (r.beta * x * n0 + gam));
+        xcl = 0;
+        if (xn < 0.0) { xn = 0.0; xcl = -1; }
+        if (xn > 1.0) { xn = 1.0; xcl = 1; }
+        if (iso) { en = e; break; }
+        double h = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) h += gc.SigE[g] * Nn[g];
+        en = e + dtau * c * (1.0 - xn) * n0 * h - dtau * cooling(r, n0, xn);
+        if (last) break;
+        if (fabs(en - e) <= 0.1 * e) break;
+        if (halvings == kMaxHalvings) { st.cap = 1; break; }
+        dtau = dtau * 0.5;
+        halvings++;
+    }
+    if (xcl) st.xclamp++;
+#pragma unroll
+    for (int g = 0; g < G; ++g) N[g] = Nn[g];
+    if (info) {
+        info->Tp = Tp;
+        info->D = D;
+        info->branch = branch;
+        info->h = halvings;
+        info->xclamp = xcl;
+    }
+    x = xn;
+    e = en;
+    rem = rem - dtau;
+    st.substeps++;
+    return true;
+}
+
 // The sub-cycled update of one cell over dt.  N[g], F[g][3] hold the
 // post-transport values on entry and the end values on exit.
-template <int G>
-__device__ inline ChemStats chem_cell(const GroupConsts &gc, const ChemParams &p, double (&N)[G],
+template <int G, bool FAST = false>
+__host__ __device__ __forceinline__ ChemStats chem_cell(const GroupConsts &gc, const ChemParams &p, double (&N)[G],
                                       double (&F)[G][3], double &x, double &T, double n0,
                                       const double (&S)[G]) {
     ChemStats st{0, 0, 0, 0};
-    const double c = p.c;
+    const bool iso = FAST ? false : (p.isothermal != 0);
     const double eunit = 1.5 * n0 * kKB;  // e = eunit (1 + x) T
     double e = eunit * (1.0 + x) * T;
     double rem = p.dt;
     while (rem > 0.0) {
-        if (!p.isothermal && !(e > 0.0 && e < HUGE_VAL)) break;  // invalid input: leave the cell
         const bool last = st.substeps >= p.max_substeps;
-        const double Tp = p.isothermal ? T : e / (eunit * (1.0 + x));
-        const RateSet r = rates_at(Tp, p.otsa);
-        double dtau = rem;
-        if (!p.isothermal && !last) {
-            double h = 0.0;
-#pragma unroll
-            for (int g = 0; g < G; ++g) h += gc.SigE[g] * N[g];
-            const double H = c * (1.0 - x) * n0 * h;
-            const double L = cooling(r, n0, x);
-            if (H != L) dtau = fmin(rem, fabs(e / (H - L)));
-        }
-        double Nn[G], inv[G], xn, en;
-        int halvings = 0;
-        for (;;) {
-            st.attempts++;
-            const double y0 = 1.0 - x;
-            double gam = 0.0;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const double kap = c * gc.sigN[g] * y0 * n0;
-                const double rec = (g == 0) ? r.dalpha * x * x * n0 * n0 : 0.0;
-                const double den = 1.0 + dtau * kap;
-                Nn[g] = (N[g] + (S[g] + rec) * dtau) / den;
-                inv[g] = den;
-                gam += c * gc.sigN[g] * Nn[g];
-            }
-            xn = 1.0 - (r.alpha * x * x * n0 * dtau + y0) / (1.0 + dtau * (r.beta * x * n0 + gam));
-            if (xn < 0.0) { xn = 0.0; st.xclamp++; }
-            if (xn > 1.0) { xn = 1.0; st.xclamp++; }
-            if (p.isothermal) { en = e; break; }
-            double h = 0.0;
-#pragma unroll
-            for (int g = 0; g < G; ++g) h += gc.SigE[g] * Nn[g];
-            en = e + dtau * c * (1.0 - xn) * n0 * h - dtau * cooling(r, n0, xn);
-            if (last) break;
-            if (fabs(en - e) <= 0.1 * e) break;
-            if (halvings == kMaxHalvings) { st.cap = 1; break; }
-            dtau = dtau * 0.5;
-            halvings++;
-        }
+        double inv[G];
+        if (!substep<G, FAST>(gc, p, last, n0, eunit, T, S, N, x, e, rem, inv, st, nullptr)) break;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            N[g] = Nn[g];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) F[g][k] = F[g][k] / inv[g];
+            for (int k = 0; k < 3; ++k) F[g][k] = F[g][k] * inv[g];
         }
-        x = xn;
-        e = en;
-        rem = rem - dtau;
-        st.substeps++;
         if (last) { st.cap = 1; break; }
-        if (p.isothermal) break;
+        if (iso) break;
     }
-    if (!p.isothermal) T = e / (eunit * (1.0 + x));
+    if (!iso) T = e / (eunit * (1.0 + x));
     return st;
 }
 

@@ -32,7 +32,7 @@ class EmmaRT:
 
     def __init__(self, shape, n_groups, dx, c_red, precision="mixed", groups=None, T_bb=1e5,
                  edges_eV=None, otsa=True, isothermal=False, max_substeps=100000,
-                 adjoint_max_steps=0, device="cuda:0"):
+                 adjoint_max_steps=0, path="fused", device="cuda:0"):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
         self.G = int(n_groups)
@@ -56,6 +56,10 @@ class EmmaRT:
         cfg.otsa, cfg.isothermal = int(bool(otsa)), int(bool(isothermal))
         cfg.max_substeps = int(max_substeps)
         cfg.adjoint_max_steps = int(adjoint_max_steps)
+        if path not in _lib.PATHS:
+            raise ValueError(f"path must be one of {sorted(_lib.PATHS)}")
+        cfg.path = _lib.PATHS[path]
+        self.path = path
         for g in range(self.G):
             cfg.sigma_N[g] = self.groups["sigma_N"][g]
             cfg.sigma_E[g] = self.groups["sigma_E"][g]
@@ -155,3 +159,51 @@ class EmmaRT:
                                        qN, qF, qx, qT, qn, qr)
         if rc != _lib.EMMA_RT_OK:
             raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))
+
+
+class RTStep(torch.autograd.Function):
+    """n_steps radiation steps as a differentiable map of (n0, src_rate, N, F, x, T).
+
+    Forward: the state is kept every K steps (checkpoints).  Backward: each
+    K-step segment is recomputed from its checkpoint inside the library (its
+    tape) and run backwards with emma_rt_step_adjoint, last segment first.
+    The context must have adjoint_max_steps >= K.
+
+        N1, F1, x1, T1 = RTStep.apply(n0, src_rate, N, F, x, T, rt, src_cell, dt, n_steps, K)
+    """
+
+    @staticmethod
+    def forward(ctx, n0, src_rate, N, F, x, T, rt, src_cell, dt, n_steps, K):
+        if K < 1 or K > rt.adjoint_max_steps:
+            raise ValueError(f"K must be in 1..{rt.adjoint_max_steps} (the context's adjoint_max_steps)")
+        N, F, x, T = N.detach().clone(), F.detach().clone(), x.detach().clone(), T.detach().clone()
+        n0d, rated = n0.detach(), src_rate.detach()
+        ckpts = []
+        done = 0
+        while done < n_steps:
+            k = min(K, n_steps - done)
+            ckpts.append((N.clone(), F.clone(), x.clone(), T.clone(), k))
+            rt.step(N, F, x, T, n0d, src_cell, rated, dt, n_steps=k)
+            done += k
+        ctx.rt, ctx.src_cell, ctx.dt, ctx.ckpts = rt, src_cell, dt, ckpts
+        ctx.save_for_backward(n0d, rated)
+        return N, F, x, T
+
+    @staticmethod
+    def backward(ctx, gN, gF, gx, gT):
+        n0, rate = ctx.saved_tensors
+        rt = ctx.rt
+        like = ctx.ckpts[0]
+
+        def grad_or_zero(g, ref):
+            return g.detach().to(ref.dtype).contiguous().clone() if g is not None else torch.zeros_like(ref)
+
+        gN, gF = grad_or_zero(gN, like[0]), grad_or_zero(gF, like[1])
+        gx, gT = grad_or_zero(gx, like[2]), grad_or_zero(gT, like[3])
+        g_n0 = torch.zeros_like(n0)
+        g_rate = torch.zeros_like(rate)
+        for (N0, F0, x0, T0, k) in reversed(ctx.ckpts):
+            rt.step_adjoint(N0, F0, x0, T0, n0, ctx.src_cell, rate, ctx.dt, k, gN, gF, gx, gT, g_n0,
+                            g_rate)
+        ctx.ckpts = None
+        return g_n0, g_rate, gN, gF, gx, gT, None, None, None, None, None

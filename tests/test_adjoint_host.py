@@ -1,0 +1,236 @@
+"""Host builds of the library's adjoint pieces against the oracle.
+
+The chemistry adjoint (chem_cell_adj) and the closure Jacobian are compiled
+for the CPU with hipcc.  Dot-product test: <w, J v> from the oracle's
+dual-number tangent equals <J^T w, v> from the library's reverse pass.  A 1^3
+periodic grid turns the oracle's step into pure chemistry (every face flux
+cancels exactly), which isolates the chemistry.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import emma_inputs as E
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1508_07888_amd", "csrc")
+
+PROG = r'''
+#include "adjoint.hpp"
+#include <cstdio>
+using namespace emma;
+template <int G> int run() {
+    GroupConsts gc; ChemParams p;
+    double Nin[G], Fin[G][3], S[G], aNo[G], aFo[G][3], x, T, n0, axo, aTo;
+    for (int g = 0; g < G; ++g) scanf("%lf %lf %lf", &gc.sigN[g], &gc.SigE[g], &gc.frac[g]);
+    scanf("%lf %lf %d %d %d", &p.c, &p.dt, &p.otsa, &p.isothermal, &p.max_substeps);
+    for (int g = 0; g < G; ++g) scanf("%lf %lf %lf %lf %lf", &Nin[g], &Fin[g][0], &Fin[g][1], &Fin[g][2], &S[g]);
+    scanf("%lf %lf %lf", &x, &T, &n0);
+    for (int g = 0; g < G; ++g) scanf("%lf %lf %lf %lf", &aNo[g], &aFo[g][0], &aFo[g][1], &aFo[g][2]);
+    scanf("%lf %lf", &axo, &aTo);
+    double aN[G], aF[G][3], aS[G], ax, aT, an0;
+    if (p.otsa && !p.isothermal)
+        chem_cell_adj<G, true>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, aN, aF, ax, aT, an0, aS);
+    else
+        chem_cell_adj<G, false>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, aN, aF, ax, aT, an0, aS);
+    for (int g = 0; g < G; ++g) printf("%.17g %.17g %.17g %.17g %.17g\n", aN[g], aF[g][0], aF[g][1], aF[g][2], aS[g]);
+    printf("%.17g %.17g %.17g\n", ax, aT, an0);
+    // forward value for a consistency check
+    double N[G], F[G][3]; for (int g = 0; g < G; ++g) { N[g] = Nin[g]; for (int k = 0; k < 3; ++k) F[g][k] = Fin[g][k]; }
+    double xx = x, TT = T;
+    ChemStats st = (p.otsa && !p.isothermal) ? chem_cell<G, true>(gc, p, N, F, xx, TT, n0, S)
+                                             : chem_cell<G, false>(gc, p, N, F, xx, TT, n0, S);
+    printf("%.17g %.17g %d\n", xx, TT, st.substeps);
+    return 0;
+}
+int main() { int G; scanf("%d", &G); if (G == 1) return run<1>(); if (G == 2) return run<2>(); return run<3>(); }
+'''
+
+
+@pytest.fixture(scope="module")
+def prog():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "adj.hip")
+    exe = os.path.join(d, "adj")
+    with open(src, "w") as fh:
+        fh.write(PROG)
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-I", CSRC, "-o", exe, src],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("hipcc host build failed: " + r.stderr[-600:])
+    return exe
+
+
+def _cell_case(seed, G, heat):
+    rng = np.random.default_rng(seed)
+    g = oracle.group_constants(E.T_BB, E.EDGES[G])
+    c = 0.1 * E.C_LIGHT
+    N = 10 ** rng.uniform(-3, 0, G) * heat
+    d = rng.standard_normal((G, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    F = d * rng.uniform(0, 0.6, (G, 1)) * c * N[:, None]
+    S = 10 ** rng.uniform(-13, -10, G) * (rng.random(G) < 0.7)
+    x = 10 ** rng.uniform(-3, -0.1)
+    T = 10 ** rng.uniform(2, 4.3)
+    n0 = 10 ** rng.uniform(-3.5, -2)
+    dt = 7e9
+    return g, c, N, F, S, x, T, n0, dt
+
+
+def _run_adj(exe, G, g, c, dt, otsa, iso, maxsub, N, F, S, x, T, n0, aN, aF, ax, aT):
+    SigE = g["sigma_E"] * g["mean_E"] - g["sigma_N"] * 13.6 * 1.602176634e-12
+    lines = [str(G)]
+    for k in range(G):
+        lines.append(f"{float(g['sigma_N'][k])!r} {float(SigE[k])!r} {float(g['frac'][k])!r}")
+    lines.append(f"{float(c)!r} {float(dt)!r} {int(otsa)} {int(iso)} {int(maxsub)}")
+    for k in range(G):
+        lines.append(" ".join(repr(float(v)) for v in (N[k], *F[k], S[k])))
+    lines.append(f"{float(x)!r} {float(T)!r} {float(n0)!r}")
+    for k in range(G):
+        lines.append(" ".join(repr(float(v)) for v in (aN[k], *aF[k])))
+    lines.append(f"{float(ax)!r} {float(aT)!r}")
+    out = subprocess.run([exe], input="\n".join(lines), capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    rows = [list(map(float, ln.split())) for ln in out[:G]]
+    ax_, aT_, an0 = map(float, out[G].split())
+    xf, Tf, nsub = out[G + 1].split()
+    aNr = np.array([r[0] for r in rows])
+    aFr = np.array([r[1:4] for r in rows])
+    aS = np.array([r[4] for r in rows])
+    return aNr, aFr, ax_, aT_, an0, aS, float(xf), float(Tf), int(nsub)
+
+
+@pytest.mark.parametrize("seed,G,heat,otsa,iso", [
+    (1, 1, 1.0, 1, 0), (2, 2, 10.0, 1, 0), (3, 3, 100.0, 1, 0), (4, 3, 1.0, 0, 0),
+    (5, 2, 30.0, 1, 1), (6, 3, 3.0, 0, 1), (7, 3, 1000.0, 1, 0), (8, 1, 0.0, 1, 0)])
+def test_chemistry_adjoint_dot_product(prog, seed, G, heat, otsa, iso):
+    g, c, N, F, S, x, T, n0, dt = _cell_case(seed, G, heat)
+    rng = np.random.default_rng(100 + seed)
+    vol = 1.0
+    # oracle: one cell, rates placed so that S = rate * frac / dx^3 with dx = 1
+    one = (1, 1, 1)
+    N3 = N.reshape(G, 1, 1, 1)
+    F3 = F.reshape(G, 3, 1, 1, 1)
+    # oracle builds S_g = rate * frac_g / vol per source: one source per group with frac 1
+    gg = {k: np.asarray(v) for k, v in g.items()}
+    # tangent direction (relative)
+    dN = N * rng.standard_normal(G)
+    dF = F * rng.standard_normal((G, 3))
+    dxh = x * (1 - x) * rng.standard_normal()
+    dT = T * rng.standard_normal()
+    dn0 = n0 * rng.standard_normal()
+    dS = S * rng.standard_normal(G)
+    # express S as G sources in the same cell, each feeding one group through frac
+    srcs = []
+    rates = []
+    for k in range(G):
+        if S[k] > 0:
+            srcs.append(0)
+            rates.append(S[k] * vol / g["frac"][k])
+    cells = np.zeros(len(srcs), dtype=np.int64)
+    rates = np.array(rates)
+    # oracle's S_g = sum_s rate_s frac_g / vol couples groups: use the library form directly
+    # instead: compare on S itself by building the tangent of rates from dS via frac
+    # (only when a single group is sourced; otherwise fix S and perturb the rest)
+    use_src = int((S > 0).sum()) == 1
+    if not use_src:
+        dS = np.zeros(G)
+        rates_s = rates[:0]
+        cells_s = cells[:0]
+        S_eff = np.zeros(G)
+    else:
+        k = int(np.nonzero(S > 0)[0][0])
+        rates_s = np.array([S[k] / g["frac"][k]])
+        cells_s = np.zeros(1, dtype=np.int64)
+        S_eff = rates_s[0] * np.asarray(g["frac"])
+        dS = S_eff * rng.standard_normal() * 0 + (S_eff / rates_s[0]) * (rates_s[0] * 0.37)
+    drate = np.array([rates_s[0] * 0.37]) if use_src else np.zeros(0)
+    kw = dict(dx=1.0, c_red=c, dt=dt, n_steps=1, groups=gg, otsa=otsa, isothermal=iso)
+    (oN, oF, ox, oT), (tN, tF, tx, tT), cnt = oracle.run_tangent(
+        N3, F3, np.full(one, x), np.full(one, T), np.full(one, n0), cells_s, rates_s,
+        dN.reshape(G, 1, 1, 1), dF.reshape(G, 3, 1, 1, 1), np.full(one, dxh), np.full(one, dT),
+        np.full(one, dn0), drate, **kw)
+    # adjoint weights
+    wN = rng.standard_normal(G) / np.maximum(np.abs(oN.reshape(G)), 1e-300)
+    wF = rng.standard_normal((G, 3)) / np.maximum(np.abs(oF.reshape(G, 3)), 1e-300)
+    wx = rng.standard_normal() / max(abs(float(ox.ravel()[0])), 1e-300)
+    wT = rng.standard_normal() / float(oT.ravel()[0])
+    if heat == 0.0:
+        wN[:] = 0.0
+        wF[:] = 0.0
+    lhs = (wN * tN.reshape(G)).sum() + (wF * tF.reshape(G, 3)).sum() + wx * float(tx.ravel()[0]) \
+        + wT * float(tT.ravel()[0])
+    aN, aF, ax, aT, an0, aS, xf, Tf, nsub = _run_adj(prog, G, g, c, dt, otsa, iso, 100000, N, F,
+                                                     S_eff, x, T, n0, wN, wF, wx, wT)
+    # forward of the host build agrees with the oracle
+    assert abs(xf - float(ox.ravel()[0])) <= 1e-12 * max(1.0, abs(xf))
+    assert abs(Tf / float(oT.ravel()[0]) - 1) <= 1e-12
+    rhs = (aN * dN).sum() + (aF * dF).sum() + ax * dxh + aT * dT + an0 * dn0 + (aS * dS).sum()
+    terms = np.abs(np.concatenate([aN * dN, (aF * dF).ravel(), [ax * dxh, aT * dT, an0 * dn0],
+                                   aS * dS]))
+    scale = max(terms.sum(), abs(lhs), 1e-300)
+    print(f"seed {seed}: substeps {nsub}, <w,Jv> {lhs:.12e}, <J^T w,v> {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-9 * scale
+
+
+JAC_PROG = r'''
+#include "adjoint.hpp"
+#include <cstdio>
+int main() {
+    double N, fx, fy, fz, c;
+    while (scanf("%lf %lf %lf %lf %lf", &N, &fx, &fy, &fz, &c) == 5) {
+        emma::ClosureJac j = emma::closure_jac(N, fx, fy, fz, c);
+        printf("%.17g %.17g %.17g %.17g %.17g\n", j.aN, j.ga, j.bq, j.bqN, j.gb);
+    }
+    return 0;
+}
+'''
+
+
+def test_closure_jacobian_matches_oracle_pressure_differences():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "jac.hip")
+    exe = os.path.join(d, "jac")
+    with open(src, "w") as fh:
+        fh.write(JAC_PROG)
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "-O1", "-I", CSRC, "-o", exe, src],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("hipcc host build failed: " + r.stderr[-400:])
+    rng = np.random.default_rng(7)
+    c = 3e9
+    cases = []
+    for f in (0.0, 0.05, 0.3, 0.7, 0.95, 1.0):
+        dvec = rng.standard_normal(3)
+        dvec /= np.linalg.norm(dvec)
+        N = 10 ** rng.uniform(-3, 1)
+        cases.append((N, *(f * c * N * dvec)))
+    inp = "\n".join(" ".join(repr(float(v)) for v in (*cs, c)) for cs in cases)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for cs, line in zip(cases, out):
+        aN, ga, bq, bqN, gb = map(float, line.split())
+        N, F = cs[0], np.array(cs[1:])
+        # analytic dP/dN and dP/dF_k from the Jacobian pieces
+        dPdN = aN * np.eye(3) + bqN * np.outer(F, F)
+        h = 1e-6
+        Fn = np.linalg.norm(F)
+        if Fn >= c * N * (1 - 1e-3):
+            # at f = 1 the clip is taken (chi = 1): one-sided difference into f > 1
+            num_N = (oracle.pressure(N, F, c) - oracle.pressure(N * (1 - h), F, c)) / (h * N)
+            assert np.allclose(dPdN, num_N, rtol=1e-5, atol=1e-8)
+            continue
+        num_N = (oracle.pressure(N * (1 + h), F, c) - oracle.pressure(N * (1 - h), F, c)) / (2 * h * N)
+        assert np.allclose(dPdN, num_N, rtol=1e-6, atol=1e-8)
+        if Fn == 0:
+            continue  # dP/dF = 0 at F = 0 (P is quadratic in F there)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1.0
+            dPdF = ga * F[k] * np.eye(3) + gb * F[k] * np.outer(F, F) + bq * (np.outer(e, F) + np.outer(F, e))
+            step = h * Fn
+            num_F = (oracle.pressure(N, F + step * e, c) - oracle.pressure(N, F - step * e, c)) / (2 * step)
+            assert np.allclose(dPdF, num_F, rtol=1e-5, atol=1e-6 * N / Fn)

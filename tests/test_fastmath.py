@@ -1,0 +1,121 @@
+"""Host builds of the library's device math: the double-precision exp/log
+(csrc/fastmath.hpp) against the C library, and the log-domain rate fits
+(csrc/physics.hpp) against the oracle's direct power-law formulas."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1508_07888_amd", "csrc")
+
+PROG = r'''
+#include "fastmath.hpp"
+#include <cstdio>
+#include <cmath>
+int main(int argc, char **argv) {
+    double x;
+    char op;
+    while (scanf(" %c %lf", &op, &x) == 2) {
+        double y = op == 'e' ? emma::exp_fp64(x) : emma::log_fp64(x);
+        printf("%.17g\n", y);
+    }
+    return 0;
+}
+'''
+
+
+def _ulps(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.abs(a - b) / np.spacing(np.abs(b))
+
+
+@pytest.fixture(scope="module")
+def prog():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "fm.hip")
+    exe = os.path.join(d, "fm")
+    with open(src, "w") as fh:
+        fh.write(PROG)
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-I", CSRC, "-o", exe, src],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("hipcc host build failed: " + r.stderr[-400:])
+    return exe
+
+
+def _run(exe, op, xs):
+    inp = "\n".join(f"{op} {float(x)!r}" for x in xs)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return np.array([float(v) for v in out.split()])
+
+
+def test_exp_within_two_ulps(prog):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.uniform(-40, 40, 3000), rng.uniform(-700, 700, 1000),
+                         [0.0, 1e-300, -1e-300, 1.0, -1.0, 0.5 * np.log(2), 700.0, -700.0]])
+    got = _run(prog, "e", xs)
+    assert np.max(_ulps(got, np.exp(xs))) <= 2.0
+    # documented clamp: 0 far below the underflow threshold, finite at the top
+    assert _run(prog, "e", [-800.0])[0] == 0.0
+    assert np.isfinite(_run(prog, "e", [800.0])[0])
+
+
+def test_log_within_two_ulps(prog):
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([10 ** rng.uniform(-300, 300, 3000), rng.uniform(0.5, 2.0, 2000),
+                         1 + 10 ** rng.uniform(-15, -1, 500), [1.0, 2.0, 0.5, 1e-308, 1.7e308]])
+    got = _run(prog, "l", xs)
+    ref = np.log(xs)
+    err = np.abs(got - ref)
+    # relative to the result, or absolute 1 ulp of 1 near x = 1 where ln x -> 0
+    assert np.all(err <= 2 * np.spacing(np.abs(ref)) + 2.3e-16 * (np.abs(ref) < 1))
+
+
+RATES_PROG = r'''
+#include "physics.hpp"
+#include <cstdio>
+int main() {
+    double T;
+    while (scanf(" %lf", &T) == 1) {
+        emma::RateSet b = emma::rates_at<true>(T), a = emma::rates_at<false>(T);
+        // alpha_B, beta, Lambda(n0=1, x=0.5) on the spot; alpha_A, Lambda case A
+        double lb = (b.crec + b.cff) * 0.25 + (b.cci + b.cce) * 0.25;
+        double la = (a.crec + a.cff) * 0.25 + (a.cci + a.cce) * 0.25;
+        printf("%.17g %.17g %.17g %.17g %.17g %.17g\n", b.alpha, b.beta, lb, a.alpha, la, a.dalpha);
+    }
+    return 0;
+}
+'''
+
+
+def test_rate_fits_match_oracle():
+    import oracle
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "rates.hip")
+    exe = os.path.join(d, "rates")
+    with open(src, "w") as fh:
+        fh.write(RATES_PROG)
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-I", CSRC, "-o", exe, src],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("hipcc host build failed: " + r.stderr[-400:])
+    Ts = np.logspace(0, 9, 400)
+    out = subprocess.run([exe], input="\n".join(repr(float(t)) for t in Ts), capture_output=True,
+                         text=True, check=True).stdout.split("\n")
+    for T, line in zip(Ts, out):
+        aB, beta, lB, aA, lA, dal = map(float, line.split())
+        ob = oracle.rates(T, n0=1.0, x=0.5, otsa=1)
+        oa = oracle.rates(T, n0=1.0, x=0.5, otsa=0)
+        assert abs(aB / ob["alpha_B"] - 1) < 1e-13
+        assert abs(aA / oa["alpha_A"] - 1) < 1e-13
+        assert abs(lB / ob["Lambda"] - 1) < 1e-13
+        assert abs(lA / oa["Lambda"] - 1) < 1e-13
+        assert abs(dal - (oa["alpha_A"] - oa["alpha_B"])) < 1e-13 * oa["alpha_A"]
+        if ob["beta"] > 1e-280:
+            # evaluated as exp(argument) with |argument| up to ~600 here: the
+            # relative error grows with the argument's size
+            assert abs(beta / ob["beta"] - 1) < 4e-16 * (10 + abs(np.log(ob["beta"])))

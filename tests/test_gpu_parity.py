@@ -50,19 +50,26 @@ def _random_case(shape, G, seed, n_src=5):
     return dict(N=N, F=F, x=x, T=T, n0=n0, cells=cells, rates=rates, dx=dx, c=c, dt=dt)
 
 
+PATHS = ["fused", "split", "reference"]
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("shape,G,seed", [((7, 9, 11), 1, 1), ((16, 5, 33), 2, 2),
                                           ((12, 12, 12), 3, 3), ((3, 20, 70), 4, 4),
-                                          ((1, 1, 1), 3, 5), ((1, 4, 64), 2, 6)])
-def test_random_grids_match_oracle(precision, shape, G, seed):
+                                          ((1, 1, 1), 3, 5), ((1, 4, 64), 2, 6),
+                                          ((9, 13, 130), 3, 7), ((40, 6, 66), 2, 8)])
+def test_random_grids_match_oracle(precision, shape, G, seed, path):
+    # ragged shapes: partial 64 x 4 tiles, z-chunks with a remainder, grids
+    # thinner than the stencil (periodic self-neighbours)
     k = _random_case(shape, G, seed)
     g = groups_for(G)
     steps = 3
     kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=steps, groups=g)
     ora = oracle.run(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], **kw)
     gpu = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
-                  precision=precision, **kw)
-    _compare(gpu, ora, precision, f"{shape} G={G}")
+                  precision=precision, path=path, **kw)
+    _compare(gpu, ora, precision, f"{shape} G={G} {path}")
     if precision == "fp64":
         d, oc = gpu[4], ora[4]
         assert d["substeps"] == oc["substeps"] and d["attempts"] == oc["attempts"]
@@ -146,17 +153,33 @@ def test_zero_steps_and_no_sources():
     _compare(gpu, ora, "fp64", "no sources")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_and_split_paths_agree(precision):
+    # same transport arithmetic and the same chemistry code in both; the fused
+    # kernel only keeps N*, F* in registers between the two
+    k = _random_case((20, 12, 70), 3, 13)
+    g = groups_for(3)
+    kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=5, groups=g, precision=precision)
+    a = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], path="fused", **kw)
+    b = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], path="split", **kw)
+    tol = 1e-14 if precision == "fp64" else 1e-6
+    for u, v in zip(a[:4], b[:4]):
+        assert normwise(u, v) <= tol
+    assert a[4]["substeps"] == b[4]["substeps"] and a[4]["limiter_hits"] == b[4]["limiter_hits"]
+
+
 def test_runs_are_bitwise_reproducible():
     k = _random_case((9, 10, 11), 3, 12)
     g = groups_for(3)
     kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=4, groups=g)
     for precision in ("fp64", "mixed"):
-        a = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
-                    precision=precision, **kw)
-        b = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
-                    precision=precision, **kw)
-        for u, v in zip(a[:4], b[:4]):
-            assert np.array_equal(u, v)
+        for path in PATHS:
+            a = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
+                        precision=precision, path=path, **kw)
+            b = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
+                        precision=precision, path=path, **kw)
+            for u, v in zip(a[:4], b[:4]):
+                assert np.array_equal(u, v)
 
 
 def test_host_errors_on_device():
