@@ -59,6 +59,103 @@ def traffic_from_profiles(kernel, workload, precision):
     return d.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30  # calibration copy: reads and writes 1 GiB
+
+
+def copy_calibration():
+    """A plain elementwise kernel of known traffic (1 GiB read, 1 GiB written),
+    run so that a counter pass sees FETCH_SIZE / WRITE_SIZE of a kernel whose
+    HBM bytes are known; the ratio scales the counters of the step kernels."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def _kernel_rows(csv_path):
+    import csv
+    with open(csv_path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _kind(name):
+    """Kernel kind and whether it is the diagnostics-free instantiation."""
+    if "emma::" not in name or "<" not in name:
+        return None, False
+    targs = [t.strip() for t in name[name.index("<") + 1:name.index(">")].split(",")]
+    diag = len(targs) > 2 and targs[2] == "true"
+    if "k_tiled" in name:
+        return ("fused_step" if targs[3] == "true" else "transport"), not diag
+    if "k_chem<" in name:
+        return "chemistry", not diag
+    if "k_transport<" in name:
+        return "transport", not diag
+    return None, False
+
+
+def summarize_pmc(fetch_dir, write_dir, workload, precision, out_dir, command):
+    """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by the ratio
+    of the known bytes of the calibration kernel to what the same counter
+    reads for it."""
+    import glob
+    counters = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per, calib = {}, []
+        for r in _kernel_rows(f):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            kind, product = _kind(r["Kernel_Name"])
+            if kind and product:
+                per.setdefault(kind, []).append(v)
+            elif "emma::" not in r["Kernel_Name"] and v > COPY_BYTES / 4:
+                calib.append(v)
+        if not calib:
+            raise RuntimeError(f"no calibration kernel found in {f}")
+        counters[counter] = (COPY_BYTES / max(calib), max(calib), {k: sum(v) / len(v) for k, v in per.items()})
+    written = []
+    for kind in counters["FETCH_SIZE"][2]:
+        ff, fc, fk = counters["FETCH_SIZE"]
+        wf, wc, wk = counters["WRITE_SIZE"]
+        if kind not in wk:
+            continue
+        d = {"kernel": kind, "workload": workload, "precision": precision, "source_hash": source_hash(),
+             "fetch_kib_raw": fk[kind] / 1024, "write_kib_raw": wk[kind] / 1024,
+             "calibration": {"bytes_each_way": COPY_BYTES, "fetch_reads_bytes": fc, "write_reads_bytes": wc,
+                             "fetch_factor": ff, "write_factor": wf},
+             "fetch_bytes_per_launch": fk[kind] * ff, "write_bytes_per_launch": wk[kind] * wf,
+             "hbm_bytes_per_launch": fk[kind] * ff + wk[kind] * wf, "commands": command}
+        path = os.path.join(out_dir, f"{kind}_{workload}_{precision}_pmc.json")
+        with open(path, "w") as fh:
+            json.dump(d, fh, indent=1)
+        written.append(path)
+    return written
+
+
+def summarize_trace(trace_dir, out_path, command):
+    """Short text summary of rocprofv3 --kernel-trace --stats (kernel stats CSV)."""
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)[0]
+    rows = _kernel_rows(f)
+    lines = ["# rocprofv3 kernel statistics", "", f"command: `{command}`", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"| {name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{float(r['Percentage']):.1f}% |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out_path
+
+
 def run_gpu(w, precision, steps, warmup, path="fused"):
     import torch
     from paper_1508_07888_amd import EmmaRT
@@ -127,7 +224,23 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--path", default="fused", choices=["fused", "split", "reference"],
                     help="kernel path (all compute the same step; fused is the product path)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for scaling rocprofv3 byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/*_pmc.json from two rocprofv3 --pmc output dirs and exit")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
+                    help="write a profiles/ text summary of a rocprofv3 --kernel-trace --stats dir and exit")
+    ap.add_argument("--summary-out", default=None, help="output file for --summarize-trace")
+    ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        out = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, "mixed",
+                            os.path.join(ROOT, "profiles"), args.command)
+        print("\n".join(out))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.summary_out, args.command))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the radiation step is built and timed on a "
               "single MI355X (no multi-GPU path in this build); run with --gpus 1",
@@ -136,6 +249,8 @@ def main():
     import emma_inputs as E
     w = E.make_workload(args.workload, n=args.n)
     G = w["G"]
+    if args.copy_calibration:
+        copy_calibration()
     mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.path)
     fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup, args.path)
 

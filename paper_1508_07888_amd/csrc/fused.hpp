@@ -223,6 +223,16 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
             buf ^= 1;
         }
 
+        // roll the z window up before the chemistry so that plane z's state and
+        // closure are dead while it runs: 2 A_z(plane z) for the next plane
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            Az2[g] = az2(cur[g], Pc[g], c);
+            cur[g] = nxt[g];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) Pc[g][q] = Pn[g][q];
+        }
+
         if (active) {
             if (FUSE) {
                 double Nc[G], Fc[G][3], Sc[G];
@@ -261,13 +271,9 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
             }
         }
 
-        // roll the window one plane up
+        // the prefetched plane z+2 becomes plane z+1 of the next iteration
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            Az2[g] = az2(cur[g], Pc[g], c);
-            cur[g] = nxt[g];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) Pc[g][q] = Pn[g][q];
             if (active) nxt[g] = nn[g];
             m1_pressure(nxt[g].n, nxt[g].fx, nxt[g].fy, nxt[g].fz, c, Pn[g]);
             if (hrole >= 0 && z + 1 < z1) hal[g] = hnext[g];

@@ -286,17 +286,23 @@ __host__ __device__ __forceinline__ ChemStats chem_cell(const GroupConsts &gc, c
     const double eunit = 1.5 * n0 * kKB;  // e = eunit (1 + x) T
     double e = eunit * (1.0 + x) * T;
     double rem = p.dt;
+    // F only ever gets multiplied by the substeps' factors: keep their product
+    double Pf[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) Pf[g] = 1.0;
     while (rem > 0.0) {
         const bool last = st.substeps >= p.max_substeps;
         double inv[G];
         if (!substep<G, FAST>(gc, p, last, n0, eunit, T, S, N, x, e, rem, inv, st, nullptr)) break;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) F[g][k] = F[g][k] * inv[g];
-        }
+        for (int g = 0; g < G; ++g) Pf[g] *= inv[g];
         if (last) { st.cap = 1; break; }
         if (iso) break;
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) F[g][k] = F[g][k] * Pf[g];
     }
     if (!iso) T = e / (eunit * (1.0 + x));
     return st;

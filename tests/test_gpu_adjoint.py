@@ -105,7 +105,7 @@ def test_adjoint64_gradient_matches_central_differences():
     g_rate = rates.grad.cpu().numpy()
     g_n0 = n0.grad
     base, d0 = _forward_loss(w, rt, st, sub, st["n0"], st["rates"], diag=True)
-    assert abs(base - float(loss)) <= 1e-12 * abs(base)
+    assert abs(base - float(loss.detach())) <= 1e-12 * abs(base)
     h = 1e-6
     r0 = st["rates"]
     stable = 0
