@@ -230,12 +230,13 @@ def main():
                     help="write profiles/*_pmc.json from two rocprofv3 --pmc output dirs and exit")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="write a profiles/ text summary of a rocprofv3 --kernel-trace --stats dir and exit")
-    ap.add_argument("--summary-out", default=None, help="output file for --summarize-trace")
+    ap.add_argument("--summary-out", default=None,
+                    help="output file for --summarize-trace, output directory for --summarize-pmc")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     args = ap.parse_args()
     if args.summarize_pmc:
         out = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, "mixed",
-                            os.path.join(ROOT, "profiles"), args.command)
+                            args.summary_out or os.path.join(ROOT, "profiles"), args.command)
         print("\n".join(out))
         return
     if args.summarize_trace:

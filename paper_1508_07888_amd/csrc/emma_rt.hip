@@ -37,6 +37,9 @@ struct emma_rt_ctx {
     double *partial;             // [nblk][G+1]
     int diag_blocks;
     double *dsum;                // [G+1]
+    uint32_t *work_count;        // [1]: cells deferred by the first chemistry pass
+    uint32_t *work_cells;        // [V]
+    int list_blocks;             // grid of the second chemistry pass
     AdjointScratch adj;
     // kernel timing (emma_rt_profile_enable)
     int prof;
@@ -151,6 +154,7 @@ extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     int64_t b = field_bytes(cfg);                          // Ns + Fs
     b += ((V + 31) / 32) * 4;                              // mask
+    b += V * 4 + 64;                                       // chemistry work list
     b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
     b += kCntSlots * CNT_COUNT * 8;
     b += ((V + 255) / 256) * (cfg->n_groups + 1) * 8 + (cfg->n_groups + 1) * 8;
@@ -169,6 +173,8 @@ static void release(emma_rt_ctx *c) {
     (void)hipFree(c->cnt);
     (void)hipFree(c->partial);
     (void)hipFree(c->dsum);
+    (void)hipFree(c->work_count);
+    (void)hipFree(c->work_cells);
     adjoint_release(c->adj);
     if (c->ev) {
         for (hipEvent_t e : *c->ev) (void)hipEventDestroy(e);
@@ -198,6 +204,14 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
     const int G = cfg->n_groups;
     c->mask_words = (V + 31) / 32;
     c->diag_blocks = (int)((V + 255) / 256);
+    {
+        // persistent second chemistry pass: a few waves per SIMD of the device
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || cus < 1)
+            cus = 256;
+        const int64_t want = (int64_t)cus * 8;
+        c->list_blocks = (int)(want < c->diag_blocks ? want : c->diag_blocks);
+    }
     struct { void **p; size_t n; } allocs[] = {
         {&c->Ns, (size_t)(G * V) * c->elem},
         {&c->Fs, (size_t)(3 * G * V) * c->elem},
@@ -208,6 +222,8 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
         {(void **)&c->cnt, (size_t)kCntSlots * CNT_COUNT * 8},
         {(void **)&c->partial, (size_t)c->diag_blocks * (G + 1) * 8},
         {(void **)&c->dsum, (size_t)(G + 1) * 8},
+        {(void **)&c->work_count, (size_t)64},
+        {(void **)&c->work_cells, (size_t)V * 4},
     };
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.n) != hipSuccess) {
@@ -256,6 +272,28 @@ static int build_sources(emma_rt_ctx *c, const int64_t *cell, const double *rate
 }
 
 // --------------------------------------------------------------- step loop
+// Second chemistry pass over the cells the first pass deferred (in = where
+// their post-transport N*, F* are, out = where the step's result goes).
+template <int G, typename S, bool DIAG>
+static int launch_chem_list(emma_rt_ctx *c, const S *inN, const S *inF, S *oN, S *oF, double *x, double *T,
+                            const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp) {
+    const WorkList wl{c->work_count, c->work_cells};
+    const unsigned nb = (unsigned)c->list_blocks;
+    Timed t(c, KID_CHEM_LIST);
+    if (cp.otsa && !cp.isothermal)
+        hipLaunchKernelGGL((k_chem_list<G, S, DIAG, true>), dim3(nb), dim3(256), 0, c->stream, inN, inF, oN, oF, x,
+                           T, n0, c->grid.V, src, gc, cp, c->cnt, wl);
+    else
+        hipLaunchKernelGGL((k_chem_list<G, S, DIAG, false>), dim3(nb), dim3(256), 0, c->stream, inN, inF, oN, oF,
+                           x, T, n0, c->grid.V, src, gc, cp, c->cnt, wl);
+    return check_launch(c, "k_chem_list");
+}
+
+static int reset_worklist(emma_rt_ctx *c) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->work_count, (int64_t)1, 0u);
+    return check_launch(c, "k_fill_u32 (work list)");
+}
+
 template <int G, typename S, bool DIAG>
 static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const double *n0, int n_src,
                      double dt, int n_steps) {
@@ -271,6 +309,7 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
     cp.isothermal = c->cfg.isothermal;
     cp.max_substeps = c->cfg.max_substeps;
     SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
+    const WorkList wl{c->work_count, c->work_cells};
     S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
     const S cr = (S)c->cfg.c_red;
     const S lam = (S)(dt / c->cfg.dx);
@@ -280,14 +319,17 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
             const bool even = (s & 1) == 0;
             S *iN = even ? N : Ns, *iF = even ? F : Fs;
             S *oN = even ? Ns : N, *oF = even ? Fs : F;
+            if (int e = reset_worklist(c)) return e;
             int e;
             {
                 Timed t(c, KID_FUSED);
                 e = launch_fused<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
-                                             dt / c->cfg.dx, c->cnt);
+                                             dt / c->cfg.dx, c->cnt, wl);
             }
             if (e) return fail(c, EMMA_RT_EHIP, "fused kernel launch failed: %s",
                                hipGetErrorString(hipGetLastError()));
+            // deferred cells: N*, F* were written to the output, finish them in place
+            if (int e2 = launch_chem_list<G, S, DIAG>(c, oN, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
         }
         if (n_steps & 1) {
             HIP_TRY(c, hipMemcpyAsync(N, Ns, (size_t)G * V * sizeof(S), hipMemcpyDeviceToDevice, c->stream));
@@ -298,24 +340,25 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
     for (int s = 0; s < n_steps; ++s) {
         if (c->cfg.path == EMMA_RT_PATH_SPLIT) {
             Timed t(c, KID_TRANSPORT);
-            launch_tiled<G, S, DIAG, false>(c->stream, N, F, Ns, Fs, x, T, n0, gr, src, gc, cp,
-                                            dt / c->cfg.dx, c->cnt);
+            launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt);
         } else {
             Timed t(c, KID_TRANSPORT);
             hipLaunchKernelGGL((k_transport<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, N, F, Ns,
                                Fs, gr, cr, lam, c->cnt);
         }
         if (int e = check_launch(c, "k_transport")) return e;
+        if (int e = reset_worklist(c)) return e;
         {
             Timed t(c, KID_CHEM);
             if (cp.otsa && !cp.isothermal)
                 hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N,
-                                   F, x, T, n0, V, src, gc, cp, c->cnt);
+                                   F, x, T, n0, V, src, gc, cp, c->cnt, wl);
             else
                 hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs,
-                                   N, F, x, T, n0, V, src, gc, cp, c->cnt);
+                                   N, F, x, T, n0, V, src, gc, cp, c->cnt, wl);
         }
         if (int e = check_launch(c, "k_chem")) return e;
+        if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
     }
     return EMMA_RT_OK;
 }
@@ -530,7 +573,7 @@ extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *
 // ------------------------------------------------------------ profiling
 static const char *kKindNames[KID_COUNT] = {"src_table", "transport", "chemistry", "fused_step",
                                             "diagnostics", "adj_chemistry", "adj_transport",
-                                            "adj_sources", "adj_forward"};
+                                            "adj_sources", "adj_forward", "chemistry_deferred"};
 
 extern "C" int emma_rt_profile_enable(emma_rt_ctx *c, int32_t enable) {
     if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");

@@ -43,6 +43,7 @@ template <typename R> struct TileArgs {
     GroupConsts gc;
     ChemParams cp;
     unsigned long long *cnt;
+    WorkList wl;
 };
 
 // Physical tile of block b when the hardware deals blocks to 8 XCDs
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
             for (int q = 0; q < 6; ++q) Pc[g][q] = Pn[g][q];
         }
 
+        bool deferred = false;
         if (active) {
             if (FUSE) {
                 double Nc[G], Fc[G][3], Sc[G];
@@ -244,23 +246,27 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
                     Fc[g][2] = (double)us[g].fz;
                 }
                 source_of<G>((int64_t)zc, a.src.mask, a.src.sorted_cell, a.src.S, a.src.n, Sc);
-                const ChemStats cs = chem_cell<G, FAST>(a.gc, a.cp, Nc, Fc, xg, Tg, n0g, Sc);
-                if (DIAG) {
-                    tot.substeps += cs.substeps;
-                    tot.attempts += cs.attempts;
-                    tot.cap += cs.cap;
-                    tot.xclamp += cs.xclamp;
-                    maxsub = max(maxsub, cs.substeps);
-                }
+                const ChemStats cs =
+                    chem_cell<G, FAST>(a.gc, a.cp, Nc, Fc, xg, Tg, n0g, Sc, kChemBudget, &deferred);
+                if (!deferred) {
+                    if (DIAG) {
+                        tot.substeps += cs.substeps;
+                        tot.attempts += cs.attempts;
+                        tot.cap += cs.cap;
+                        tot.xclamp += cs.xclamp;
+                        maxsub = max(maxsub, cs.substeps);
+                    }
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    us[g].n = (R)Nc[g];
-                    us[g].fx = (R)Fc[g][0];
-                    us[g].fy = (R)Fc[g][1];
-                    us[g].fz = (R)Fc[g][2];
+                    for (int g = 0; g < G; ++g) {
+                        us[g].n = (R)Nc[g];
+                        us[g].fx = (R)Fc[g][0];
+                        us[g].fy = (R)Fc[g][1];
+                        us[g].fz = (R)Fc[g][2];
+                    }
+                    st(a.x, zc * 8u, xg);
+                    st(a.T, zc * 8u, Tg);
                 }
-                st(a.x, zc * 8u, xg);
-                st(a.T, zc * 8u, Tg);
+                // deferred: N*, F* go to the output below; x, T stay untouched
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -270,6 +276,8 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
                 st(a.Fo + (int64_t)(3 * g + 2) * V, zc * E, us[g].fz);
             }
         }
+
+        if (FUSE) defer_push(a.wl, deferred, zc);
 
         // the prefetched plane z+2 becomes plane z+1 of the next iteration
 #pragma unroll
@@ -296,7 +304,7 @@ template <int G, typename S>
 inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, double *T,
                              const double *n0, const Grid &gr, const SrcTable &src,
                              const GroupConsts &gc, const ChemParams &cp, double lam,
-                             unsigned long long *cnt, int LZ) {
+                             unsigned long long *cnt, int LZ, WorkList wl) {
     TileArgs<S> a;
     a.N = iN; a.F = iF; a.No = oN; a.Fo = oF;
     a.x = x; a.T = T; a.n0 = n0;
@@ -311,6 +319,7 @@ inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, 
     a.gc = gc;
     a.cp = cp;
     a.cnt = cnt;
+    a.wl = wl;
     return a;
 }
 
@@ -326,25 +335,34 @@ inline int pick_lz(const Grid &gr) {
 // double fields: V * 8 bytes must stay below 4 GiB.
 inline bool tiled_supported(const Grid &gr) { return (uint64_t)gr.V * 8 < ((uint64_t)1 << 32); }
 
-template <int G, typename S, bool DIAG, bool FUSE>
-inline int launch_tiled(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, double *x, double *T,
-                        const double *n0, const Grid &gr, const SrcTable &src, const GroupConsts &gc,
-                        const ChemParams &cp, double lam, unsigned long long *cnt) {
+// Transport only (split path): one group per block, grid.y = group, which
+// keeps one group's rolling window in registers instead of all G.
+template <int G, typename S, bool DIAG>
+inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
+                                  const ChemParams &cp, double lam, unsigned long long *cnt) {
     const int LZ = pick_lz(gr);
-    TileArgs<S> a = tile_args<G, S>(iN, iF, oN, oF, x, T, n0, gr, src, gc, cp, lam, cnt, LZ);
-    const int nb = a.ntx * a.nty * a.ntz;
-    if (cp.otsa && !cp.isothermal)
-        hipLaunchKernelGGL((k_tiled<G, S, DIAG, FUSE, true>), dim3(nb), dim3(kTX * kTY), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_tiled<G, S, DIAG, FUSE, false>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+    for (int g = 0; g < G; ++g) {
+        TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
+                                        oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
+                                        GroupConsts{}, cp, lam, cnt, LZ, WorkList{});
+        const int nb = a.ntx * a.nty * a.ntz;
+        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <int G, typename S, bool DIAG>
 inline int launch_fused(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, double *x, double *T,
                         const double *n0, const Grid &gr, const SrcTable &src, const GroupConsts &gc,
-                        const ChemParams &cp, double lam, unsigned long long *cnt) {
-    return launch_tiled<G, S, DIAG, true>(st, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp, lam, cnt);
+                        const ChemParams &cp, double lam, unsigned long long *cnt, WorkList wl) {
+    const int LZ = pick_lz(gr);
+    TileArgs<S> a = tile_args<G, S>(iN, iF, oN, oF, x, T, n0, gr, src, gc, cp, lam, cnt, LZ, wl);
+    const int nb = a.ntx * a.nty * a.ntz;
+    if (cp.otsa && !cp.isothermal)
+        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, true>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, false>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace emma

@@ -47,6 +47,7 @@ enum KernelKind {
     KID_ADJ_TRANSPORT,
     KID_ADJ_SRC,
     KID_ADJ_FWD,
+    KID_CHEM_LIST,
     KID_COUNT
 };
 
@@ -261,17 +262,42 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
 }
 
 // ---------------------------------------------------------------- chemistry
+// Work list of cells whose subcycle did not finish within the first pass's
+// substep budget.  Most cells need one or two substeps; the few heated cells
+// near the sources need tens to hundreds, and in place they would hold their
+// whole wave for that long.  They are finished by a second, persistent pass
+// over the compacted list (same code, same inputs, same results).
+constexpr int kChemBudget = 4;
+
+struct WorkList {
+    uint32_t *count;  // [1], reset before every first pass
+    uint32_t *cells;  // [V]
+};
+
+// Appends cell i for every lane with defer set: one atomic per wave.
+__device__ inline void defer_push(const WorkList &wl, bool defer, uint32_t i) {
+    const unsigned long long m = __ballot(defer);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == __ffsll((long long)m) - 1) base = atomicAdd(wl.count, (uint32_t)__popcll(m));
+    base = __shfl(base, __ffsll((long long)m) - 1, 64);
+    if (defer) wl.cells[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
-// gas state and the cell's source density; writes the end-of-step N, F, x, T.
+// gas state and the cell's source density; writes the end-of-step N, F, x, T,
+// or defers the cell (budget exhausted: nothing written).
 template <int G, typename S, bool DIAG, bool FAST>
 __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S *__restrict__ Fs,
                                               S *__restrict__ N, S *__restrict__ F,
                                               double *__restrict__ x, double *__restrict__ T,
                                               const double *__restrict__ n0, int64_t V,
                                               SrcTable src, GroupConsts gc, ChemParams cp,
-                                              unsigned long long *cnt) {
+                                              unsigned long long *cnt, WorkList wl) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ChemStats st{0, 0, 0, 0};
+    bool deferred = false;
     if (i < V) {
         double Nc[G], Fc[G][3], Sc[G];
 #pragma unroll
@@ -282,22 +308,76 @@ __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S 
         }
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
         double xc = x[i], Tc = T[i];
-        st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc);
+        st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc, kChemBudget, &deferred);
+        if (!deferred) {
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            N[(int64_t)g * V + i] = (S)Nc[g];
+            for (int g = 0; g < G; ++g) {
+                N[(int64_t)g * V + i] = (S)Nc[g];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + i] = (S)Fc[g][k];
+                for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + i] = (S)Fc[g][k];
+            }
+            x[i] = xc;
+            T[i] = Tc;
+        } else {
+            st = ChemStats{0, 0, 0, 0};
         }
-        x[i] = xc;
-        T[i] = Tc;
     }
+    defer_push(wl, deferred, (uint32_t)i);
     if (DIAG) {
         wave_count(cnt, CNT_SUB, st.substeps);
         wave_count(cnt, CNT_ATT, st.attempts);
         wave_count(cnt, CNT_CAP, st.cap);
         wave_count(cnt, CNT_XCLAMP, st.xclamp);
         wave_count_max(cnt, CNT_MAXSUB, st.substeps);
+    }
+}
+
+// Second pass: the deferred cells, whole subcycle, grid-stride over the list.
+// Ns, Fs hold the post-transport values (they may alias N, F: each cell is
+// read before it is written by the same thread).
+template <int G, typename S, bool DIAG, bool FAST>
+__global__ __launch_bounds__(256) void k_chem_list(const S *Ns, const S *Fs, S *N, S *F, double *__restrict__ x,
+                                                   double *__restrict__ T, const double *__restrict__ n0,
+                                                   int64_t V, SrcTable src, GroupConsts gc, ChemParams cp,
+                                                   unsigned long long *cnt, WorkList wl) {
+    const uint32_t n = *wl.count;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    ChemStats tot{0, 0, 0, 0};
+    int maxsub = 0;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int64_t i = wl.cells[k];
+        double Nc[G], Fc[G][3], Sc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            Nc[g] = (double)Ns[(int64_t)g * V + i];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) Fc[g][q] = (double)Fs[((int64_t)g * 3 + q) * V + i];
+        }
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        double xc = x[i], Tc = T[i];
+        const ChemStats st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            N[(int64_t)g * V + i] = (S)Nc[g];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) F[((int64_t)g * 3 + q) * V + i] = (S)Fc[g][q];
+        }
+        x[i] = xc;
+        T[i] = Tc;
+        if (DIAG) {
+            tot.substeps += st.substeps;
+            tot.attempts += st.attempts;
+            tot.cap += st.cap;
+            tot.xclamp += st.xclamp;
+            maxsub = max(maxsub, st.substeps);
+        }
+    }
+    if (DIAG) {
+        wave_count(cnt, CNT_SUB, tot.substeps);
+        wave_count(cnt, CNT_ATT, tot.attempts);
+        wave_count(cnt, CNT_CAP, tot.cap);
+        wave_count(cnt, CNT_XCLAMP, tot.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, maxsub);
     }
 }
 

@@ -276,11 +276,15 @@ __host__ __device__ __forceinline__ bool substep(const GroupConsts &gc, const Ch
 }
 
 // The sub-cycled update of one cell over dt.  N[g], F[g][3] hold the
-// post-transport values on entry and the end values on exit.
+// post-transport values on entry and the end values on exit.  With a finite
+// budget the cell gives up after that many accepted substeps if dt is not
+// covered yet (*deferred = true; the outputs are then meaningless and the
+// caller recomputes the cell later from its inputs).
 template <int G, bool FAST = false>
 __host__ __device__ __forceinline__ ChemStats chem_cell(const GroupConsts &gc, const ChemParams &p, double (&N)[G],
                                       double (&F)[G][3], double &x, double &T, double n0,
-                                      const double (&S)[G]) {
+                                      const double (&S)[G], int budget = 0x7fffffff,
+                                      bool *deferred = nullptr) {
     ChemStats st{0, 0, 0, 0};
     const bool iso = FAST ? false : (p.isothermal != 0);
     const double eunit = 1.5 * n0 * kKB;  // e = eunit (1 + x) T
@@ -291,6 +295,10 @@ __host__ __device__ __forceinline__ ChemStats chem_cell(const GroupConsts &gc, c
 #pragma unroll
     for (int g = 0; g < G; ++g) Pf[g] = 1.0;
     while (rem > 0.0) {
+        if (st.substeps >= budget) {
+            *deferred = true;
+            return st;
+        }
         const bool last = st.substeps >= p.max_substeps;
         double inv[G];
         if (!substep<G, FAST>(gc, p, last, n0, eunit, T, S, N, x, e, rem, inv, st, nullptr)) break;
