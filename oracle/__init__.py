@@ -50,6 +50,11 @@ def lib():
         L.oracle_face_flux.restype = None
         L.oracle_face_flux.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp,
                                        ctypes.c_int, ctypes.c_double, _dp]
+        L.oracle_hll_flux.restype = None
+        L.oracle_hll_flux.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp,
+                                      ctypes.c_int, ctypes.c_double, _dp]
+        L.oracle_m1_speeds.restype = None
+        L.oracle_m1_speeds.argtypes = [ctypes.c_double, _dp, ctypes.c_int, ctypes.c_double, _dp]
         L.oracle_rates.restype = None
         L.oracle_rates.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, _dp]
@@ -71,10 +76,20 @@ def _f64(a):
     return a
 
 
-def _pack(shape, G, dx, c_red, dt, groups, otsa=1, isothermal=0, max_substeps=100000):
+BC = {"periodic": 0, "transmissive": 1, "reflective": 2, "inflow": 3}
+FLUX = {"glf": 0, "hll": 1}
+
+
+def _pack(shape, G, dx, c_red, dt, groups, otsa=1, isothermal=0, max_substeps=100000,
+          bc=None, inflow=None, flux="glf"):
+    """``bc``: six face kinds (x-, x+, y-, y+, z-, z+), names of BC or ints;
+    ``inflow``: six photon flux densities (photons cm^-2 s^-1) for inflow faces."""
     nz, ny, nx = shape
-    ints = np.array([nx, ny, nz, G, otsa, isothermal, max_substeps], dtype=np.int32)
-    dbls = np.array([dx, c_red, dt], dtype=np.float64)
+    bc = [0] * 6 if bc is None else [BC[b] if isinstance(b, str) else int(b) for b in bc]
+    inflow = [0.0] * 6 if inflow is None else [float(v) for v in inflow]
+    fl = FLUX[flux] if isinstance(flux, str) else int(flux)
+    ints = np.array([nx, ny, nz, G, otsa, isothermal, max_substeps] + bc + [fl], dtype=np.int32)
+    dbls = np.array([dx, c_red, dt] + inflow, dtype=np.float64)
     gr = np.zeros((4, 4), dtype=np.float64)
     for r, key in enumerate(("sigma_N", "sigma_E", "mean_E", "frac")):
         v = np.asarray(groups[key], dtype=np.float64)
@@ -87,13 +102,15 @@ def _counters(c):
 
 
 def run(N, F, x, T, n0, src_cell, src_rate, *, dx, c_red, dt, n_steps, groups,
-        otsa=1, isothermal=0, max_substeps=100000, return_substeps=False):
+        otsa=1, isothermal=0, max_substeps=100000, return_substeps=False, bc=None, inflow=None,
+        flux="glf"):
     """Advance (N, F, x, T) by ``n_steps`` steps of ``dt``; returns copies and
     the counter dict (and per-cell accepted-substep totals if asked)."""
     N = _f64(N).copy(); F = _f64(F).copy(); x = _f64(x).copy(); T = _f64(T).copy()
     n0 = _f64(n0)
     G = N.shape[0]
-    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps)
+    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps,
+                           bc, inflow, flux)
     sc = np.ascontiguousarray(src_cell, dtype=np.int64)
     sr = _f64(src_rate)
     sub = np.zeros(n0.size, dtype=np.int64)
@@ -111,7 +128,8 @@ def run(N, F, x, T, n0, src_cell, src_rate, *, dx, c_red, dt, n_steps, groups,
 
 
 def run_tangent(N, F, x, T, n0, src_cell, src_rate, dN, dF, dxh, dT, dn0, drate, *,
-                dx, c_red, dt, n_steps, groups, otsa=1, isothermal=0, max_substeps=100000):
+                dx, c_red, dt, n_steps, groups, otsa=1, isothermal=0, max_substeps=100000,
+                bc=None, inflow=None, flux="glf"):
     """Forward run carried in dual numbers: returns the end state, its
     directional derivative along (dN, dF, dxh, dT, dn0, drate), and counters."""
     N = _f64(N).copy(); F = _f64(F).copy(); x = _f64(x).copy(); T = _f64(T).copy()
@@ -120,7 +138,8 @@ def run_tangent(N, F, x, T, n0, src_cell, src_rate, dN, dF, dxh, dT, dn0, drate,
     sc = np.ascontiguousarray(src_cell, dtype=np.int64)
     sr = _f64(src_rate); dr = _f64(drate)
     G = N.shape[0]
-    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps)
+    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps,
+                           bc, inflow, flux)
     cnt = np.zeros(7, dtype=np.int64)
     rc = lib().oracle_run_tangent(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), int(n_steps),
                                   _d(N), _d(F), _d(x), _d(T), _d(n0),
@@ -132,12 +151,14 @@ def run_tangent(N, F, x, T, n0, src_cell, src_rate, dN, dF, dxh, dT, dn0, drate,
     return (N, F, x, T), (dN, dF, dxh, dT), _counters(cnt)
 
 
-def transport(N, F, *, dx, c_red, dt):
-    """One conservative transport update (no chemistry) of every group."""
+def transport(N, F, *, dx, c_red, dt, bc=None, inflow=None, flux="glf", frac=None):
+    """One conservative transport update (no chemistry) of every group;
+    ``frac`` splits an inflow face's photon flux over the groups."""
     N = _f64(N); F = _f64(F)
     G = N.shape[0]
-    dummy = {"sigma_N": [0] * 4, "sigma_E": [0] * 4, "mean_E": [0] * 4, "frac": [0] * 4}
-    ints, dbls, gr = _pack(N.shape[1:], G, dx, c_red, dt, dummy)
+    fr = [0.0] * 4 if frac is None else list(frac) + [0.0] * (4 - len(frac))
+    dummy = {"sigma_N": [0] * 4, "sigma_E": [0] * 4, "mean_E": [0] * 4, "frac": fr}
+    ints, dbls, gr = _pack(N.shape[1:], G, dx, c_red, dt, dummy, bc=bc, inflow=inflow, flux=flux)
     Ns = np.empty_like(N); Fs = np.empty_like(F)
     cnt = np.zeros(7, dtype=np.int64)
     rc = lib().oracle_transport(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), _d(N), _d(F),
@@ -172,6 +193,19 @@ def face_flux(NL, FL, NR, FR, d, c):
     FL = _f64(FL); FR = _f64(FR); out = np.empty(4, dtype=np.float64)
     lib().oracle_face_flux(float(NL), _d(FL), float(NR), _d(FR), int(d), float(c), _d(out))
     return out
+
+
+def hll_flux(NL, FL, NR, FR, d, c):
+    FL = _f64(FL); FR = _f64(FR); out = np.empty(4, dtype=np.float64)
+    lib().oracle_hll_flux(float(NL), _d(FL), float(NR), _d(FR), int(d), float(c), _d(out))
+    return out
+
+
+def m1_speeds(N, F, d, c):
+    """(lambda-, lambda+) along axis d."""
+    F = _f64(F); out = np.empty(2, dtype=np.float64)
+    lib().oracle_m1_speeds(float(N), _d(F), int(d), float(c), _d(out))
+    return float(out[0]), float(out[1])
 
 
 def rates(T, n0=1.0, x=0.5, otsa=1):

@@ -45,6 +45,20 @@
  *       otherwise alpha = alpha_A and (alpha_A - alpha_B) x^2 n0^2 photons
  *       go to group 1.
  *   R15 isothermal validation mode: one substep of dt, no energy update.
+ *   R16 global boundaries (Sec. 4, gather step): periodic by default; a
+ *       transmissive face takes the cell itself as its outside neighbour, a
+ *       reflective face the cell with the face-normal flux component
+ *       reversed (a mirror); both faces of an axis are periodic or neither.
+ *   R17 planar source (photo-evaporation test of Sec. 6): an inflow face's
+ *       outside neighbour is a beam entering the domain along the face
+ *       normal, F = Phi_g n_in and N = Phi_g / c (f = 1), where Phi_g is the
+ *       face's photon flux density times the group's photon fraction.
+ *   R18 the HLL flux "on the way" in Sec. 2.2.3 takes as signal speeds along
+ *       axis d the eigenvalues of the one-dimensional M1 system (N, F_d) at
+ *       the normal reduced flux f_d = F_d/(c N) (clipped to [-1, 1], 0 when
+ *       N <= 0): c (chi' +- sqrt(chi'^2 + 4 (chi - f_d chi')))/2, with chi
+ *       and chi' = dchi/df at f_d; left speed min over both states and 0,
+ *       right speed max over both states and 0.
  */
 #include <cmath>
 #include <cstdint>
@@ -113,10 +127,17 @@ template <class R> inline R rmin(R a, R b) { return (b < a) ? b : a; }
 template <class R> inline R rmax(R a, R b) { return (a < b) ? b : a; }
 
 /* --------------------------------------------------------------- parameters */
+/* Boundary kinds of the faces x-, x+, y-, y+, z-, z+ (R16, R17) and the flux
+ * functions (R1, R18). */
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
+enum { FLUX_GLF = 0, FLUX_HLL = 1 };
+
 struct Params {
     int nx, ny, nz, G;
     double dx, c, dt;
     int otsa, isothermal, max_substeps;
+    int bc[6], flux;
+    double inflow[6]; /* photons cm^-2 s^-1 entering through an inflow face */
     double sigN[4], sigE[4], meanE[4], frac[4];
     double SigmaE[4]; /* sigma_E <E> - sigma_N E_13.6, Sec. 2.2.4 */
 };
@@ -200,8 +221,84 @@ void glf_flux(R NL, const R FL[3], R NR, const R FR[3], int d, double c,
         fluxF[k] = 0.5 * c * c * (PL[k][d] + PR[k][d]) - 0.5 * c * (FR[k] - FL[k]);
 }
 
-/* One conservative transport update of every group on the periodic grid
- * (eq. e:uprt, 3D unsplit, R5), from the old state (N, F) into (Ns, Fs),
+/* Levermore's chi and its derivative in f (R3), for the wave speeds. */
+template <class R> R chi_of(R f) { return (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f)); }
+template <class R> R dchi_df(R f) {
+    R s = sqrt(4.0 - 3.0 * f * f);
+    R den = 5.0 + 2.0 * s;
+    /* d/df of (3 + 4f^2)/(5 + 2s) with ds/df = -3f/s */
+    return (8.0 * f * den + (3.0 + 4.0 * f * f) * 6.0 * f / s) / (den * den);
+}
+
+/* Signal speeds along axis d of one state (R18). */
+template <class R> void m1_speeds(R N, const R F[3], int d, double c, R &lmin, R &lmax) {
+    R f = R(0.0);
+    if (N > R(0.0)) f = rmax(R(-1.0), rmin(R(1.0), F[d] / (c * N)));
+    R chi = chi_of(f), dchi = dchi_df(f);
+    /* the radicand is (1 - f)^2-small near |f| = 1 and may round below 0 */
+    R root = sqrt(rmax(R(0.0), dchi * dchi + 4.0 * (chi - f * dchi)));
+    lmin = 0.5 * c * (dchi - root);
+    lmax = 0.5 * c * (dchi + root);
+}
+
+/* HLL flux across a face normal to axis d (R18):
+ *   flux = (a+ Ft(U_L) - a- Ft(U_R) + a+ a- (U_R - U_L)) / (a+ - a-),
+ * Ft_d(U) = (F_d, c^2 P_.d), a- = min(0, speeds), a+ = max(0, speeds).
+ * With a+- = +-c it is the flux of eq. (e:glf). */
+template <class R>
+void hll_flux(R NL, const R FL[3], R NR, const R FR[3], int d, double c, R &fluxN, R fluxF[3]) {
+    R PL[3][3], PR[3][3];
+    m1_pressure(NL, FL, c, PL);
+    m1_pressure(NR, FR, c, PR);
+    R lminL, lmaxL, lminR, lmaxR;
+    m1_speeds(NL, FL, d, c, lminL, lmaxL);
+    m1_speeds(NR, FR, d, c, lminR, lmaxR);
+    R am = rmin(R(0.0), rmin(lminL, lminR));
+    R ap = rmax(R(0.0), rmax(lmaxL, lmaxR));
+    R inv = 1.0 / (ap - am);
+    fluxN = (ap * FL[d] - am * FR[d] + ap * am * (NR - NL)) * inv;
+    for (int k = 0; k < 3; ++k)
+        fluxF[k] = (ap * c * c * PL[k][d] - am * c * c * PR[k][d] + ap * am * (FR[k] - FL[k])) * inv;
+}
+
+template <class R>
+void face_flux(const Params &p, R NL, const R FL[3], R NR, const R FR[3], int d, R &fluxN, R fluxF[3]) {
+    if (p.flux == FLUX_HLL) hll_flux(NL, FL, NR, FR, d, p.c, fluxN, fluxF);
+    else glf_flux(NL, FL, NR, FR, d, p.c, fluxN, fluxF);
+}
+
+/* The neighbour of cell (x, y, z) of group g on side s (-1 or +1) of axis d:
+ * the next cell, across a periodic face the cell on the far side of the grid,
+ * and across any other face the outside state of R16/R17. */
+template <class R>
+void neighbour(const Params &p, const R *Ng, const R *Fg, int g, int x, int y, int z, int d, int s,
+               R &Nn, R Fn[3]) {
+    const int64_t V = (int64_t)p.nx * p.ny * p.nz;
+    int c3[3] = {x, y, z};
+    const int n3[3] = {p.nx, p.ny, p.nz};
+    const int face = 2 * d + (s > 0 ? 1 : 0);
+    int q = c3[d] + s;
+    int kind = BC_PERIODIC;
+    if (q < 0 || q >= n3[d]) {
+        kind = p.bc[face];
+        q = (kind == BC_PERIODIC) ? (q + n3[d]) % n3[d] : c3[d];
+    }
+    c3[d] = q;
+    const int64_t j = cell_index(p, c3[0], c3[1], c3[2]);
+    Nn = Ng[j];
+    for (int k = 0; k < 3; ++k) Fn[k] = Fg[k * V + j];
+    if (kind == BC_REFLECTIVE) {
+        Fn[d] = -Fn[d];
+    } else if (kind == BC_INFLOW) {
+        const double phi = p.inflow[face] * p.frac[g];
+        Nn = R(phi / p.c);
+        for (int k = 0; k < 3; ++k) Fn[k] = R(0.0);
+        Fn[d] = R(s < 0 ? phi : -phi); /* pointing into the domain */
+    }
+}
+
+/* One conservative transport update of every group (eq. e:uprt, 3D unsplit,
+ * R5; boundaries R16, R17; flux R1 or R18), from the old state (N, F) into (Ns, Fs),
  * followed by the floor N* >= 0 and the limiter |F*| <= c N* (R13).
  * Layout: N[g][z][y][x], F[g][k][z][y][x]. */
 template <class R>
@@ -219,16 +316,12 @@ void transport(const Params &p, const R *N, const R *F, R *Ns, R *Fs, Counters &
             R accN = R(0.0);
             R accF[3] = {R(0.0), R(0.0), R(0.0)};
             for (int d = 0; d < 3; ++d) {
-                int xm = x, ym = y, zm = z, xp = x, yp = y, zp = z;
-                if (d == 0) { xm = (x + p.nx - 1) % p.nx; xp = (x + 1) % p.nx; }
-                if (d == 1) { ym = (y + p.ny - 1) % p.ny; yp = (y + 1) % p.ny; }
-                if (d == 2) { zm = (z + p.nz - 1) % p.nz; zp = (z + 1) % p.nz; }
-                int64_t im = cell_index(p, xm, ym, zm), ip = cell_index(p, xp, yp, zp);
-                R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
-                R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
+                R Nm, Fm[3], Np, Fp[3];
+                neighbour(p, Ng, Fg, g, x, y, z, d, -1, Nm, Fm);
+                neighbour(p, Ng, Fg, g, x, y, z, d, +1, Np, Fp);
                 R lo_N, lo_F[3], hi_N, hi_F[3];
-                glf_flux(Ng[im], Fm, Ng[i], Fi, d, p.c, lo_N, lo_F);   /* face i-1/2 */
-                glf_flux(Ng[i], Fi, Ng[ip], Fp, d, p.c, hi_N, hi_F);   /* face i+1/2 */
+                face_flux(p, Nm, Fm, Ng[i], Fi, d, lo_N, lo_F);   /* face i-1/2 */
+                face_flux(p, Ng[i], Fi, Np, Fp, d, hi_N, hi_F);   /* face i+1/2 */
                 accN += lo_N - hi_N;
                 for (int k = 0; k < 3; ++k) accF[k] += lo_F[k] - hi_F[k];
             }
@@ -432,8 +525,17 @@ void group_constants(double Tbb, const double *edges_eV, int G, int panels,
 bool fill_params(Params &p, const int *ints, const double *dbls, const double *groups) {
     p.nx = ints[0]; p.ny = ints[1]; p.nz = ints[2]; p.G = ints[3];
     p.otsa = ints[4]; p.isothermal = ints[5]; p.max_substeps = ints[6];
+    for (int f = 0; f < 6; ++f) p.bc[f] = ints[7 + f];
+    p.flux = ints[13];
     p.dx = dbls[0]; p.c = dbls[1]; p.dt = dbls[2];
+    for (int f = 0; f < 6; ++f) p.inflow[f] = dbls[3 + f];
     if (p.G < 1 || p.G > 4 || p.nx < 1 || p.ny < 1 || p.nz < 1) return false;
+    if (p.flux != FLUX_GLF && p.flux != FLUX_HLL) return false;
+    for (int d = 0; d < 3; ++d) {
+        const int a = p.bc[2 * d], b = p.bc[2 * d + 1];
+        if (a < BC_PERIODIC || a > BC_INFLOW || b < BC_PERIODIC || b > BC_INFLOW) return false;
+        if ((a == BC_PERIODIC) != (b == BC_PERIODIC)) return false;
+    }
     for (int g = 0; g < p.G; ++g) {
         p.sigN[g] = groups[0 * 4 + g];
         p.sigE[g] = groups[1 * 4 + g];
@@ -453,8 +555,8 @@ void export_counters(const Counters &c, int64_t *out) {
 } /* namespace */
 
 /* ===================================================================== C ABI */
-/* ints:  [nx, ny, nz, G, otsa, isothermal, max_substeps]
- * dbls:  [dx (cm), c_red (cm/s), dt (s)]
+/* ints:  [nx, ny, nz, G, otsa, isothermal, max_substeps, bc x- x+ y- y+ z- z+, flux]
+ * dbls:  [dx (cm), c_red (cm/s), dt (s), inflow x- x+ y- y+ z- z+ (photons cm^-2 s^-1)]
  * groups: 4x4 row-major [sigma_N; sigma_E; <E> (erg); source fraction], first G used
  * counters (optional, 7): limiter, N<0 clamps, x clamps, cap hits,
  *                         accepted substeps, attempts, max substeps in a cell   */
@@ -549,6 +651,21 @@ void oracle_pressure(double N, const double *F, double c, double *P) {
     m1_pressure<double>(N, Fl, c, Pm);
     for (int k = 0; k < 3; ++k)
         for (int d = 0; d < 3; ++d) P[k * 3 + d] = Pm[k][d];
+}
+
+/* Signal speeds of R18 along axis d: out[0] = lambda-, out[1] = lambda+. */
+void oracle_m1_speeds(double N, const double *F, int d, double c, double *out) {
+    double Fl[3] = {F[0], F[1], F[2]};
+    m1_speeds<double>(N, Fl, d, c, out[0], out[1]);
+}
+
+/* HLL face flux of R18 along axis d: out[0] for N, out[1..3] for F. */
+void oracle_hll_flux(double NL, const double *FL, double NR, const double *FR, int d,
+                     double c, double *out) {
+    double fl[3] = {FL[0], FL[1], FL[2]}, fr[3] = {FR[0], FR[1], FR[2]};
+    double fN, fF[3];
+    hll_flux<double>(NL, fl, NR, fr, d, c, fN, fF);
+    out[0] = fN; out[1] = fF[0]; out[2] = fF[1]; out[3] = fF[2];
 }
 
 /* Face flux of eq. (e:glf) along axis d: out[0] for N, out[1..3] for F. */
