@@ -2,12 +2,14 @@
  * emma_rt.h -- C ABI of the MI355X radiation step library (libemma_rt.so).
  *
  * One call advances the coarse-grid radiation of the EMMA code (Aubert,
- * Deparis & Ocvirk 2015) by n_steps explicit steps on a uniform periodic grid
+ * Deparis & Ocvirk 2015) by n_steps explicit steps on a uniform grid (periodic,
+ * or with the transmissive / reflective / inflow faces of Sec. 4 and Sec. 6)
  * with the gas frozen, as the coarse radiative transport approximation (Sec. 5)
  * does between two dynamical steps.  Each step is
  *   1. the M1 transport of every frequency group (Sec. 2.2.3): Eddington
  *      tensor closure, Lax-Friedrichs / HLL(+-c_red) face fluxes (eq. e:glf)
- *      and the unsplit conservative update (eq. e:uprt), then
+ *      or HLL with M1 wave speeds, and the unsplit conservative update
+ *      (eq. e:uprt), then
  *   2. the per-cell sub-cycled hydrogen thermochemistry (Sec. 2.2.4):
  *      source injection, photo-ionisation, recombination, collisional
  *      ionisation, heating and cooling, coupled back into N and F.
@@ -51,6 +53,23 @@ typedef enum {
 
 typedef enum { EMMA_RT_FP64 = 0, EMMA_RT_MIXED = 1 } emma_rt_precision;
 typedef enum { EMMA_RT_PATH_FUSED = 0, EMMA_RT_PATH_SPLIT = 1, EMMA_RT_PATH_REFERENCE = 2 } emma_rt_path;
+/* Global boundary of one face (Sec. 4, gather step; Sec. 6 test set-ups).
+ * Across a non-periodic face the outside neighbour of a boundary cell is:
+ *   TRANSMISSIVE  the cell itself;
+ *   REFLECTIVE    the cell with its face-normal flux component reversed;
+ *   INFLOW        a planar source: a beam entering along the face normal with
+ *                 photon flux density inflow[face] (photons cm^-2 s^-1) split
+ *                 over the groups by src_frac, N = flux / c_red (f = 1). */
+typedef enum {
+    EMMA_RT_BC_PERIODIC = 0,
+    EMMA_RT_BC_TRANSMISSIVE = 1,
+    EMMA_RT_BC_REFLECTIVE = 2,
+    EMMA_RT_BC_INFLOW = 3
+} emma_rt_bc;
+/* Face flux: GLF = eq. (e:glf), HLL with signal speeds +-c_red;
+ * HLL = HLL with, along axis d, the eigenvalues of the one-dimensional M1
+ * system at the normal reduced flux F_d/(c_red N) as signal speeds. */
+typedef enum { EMMA_RT_FLUX_GLF = 0, EMMA_RT_FLUX_HLL = 1 } emma_rt_flux;
 
 #define EMMA_RT_MAX_GROUPS 4
 #define EMMA_RT_MAX_SOURCES 65536
@@ -80,6 +99,13 @@ typedef struct {
     double sigma_E[EMMA_RT_MAX_GROUPS];
     double mean_E[EMMA_RT_MAX_GROUPS];
     double src_frac[EMMA_RT_MAX_GROUPS];
+    /* Faces in the order x-, x+, y-, y+, z-, z+; emma_rt_bc values, 0 (periodic)
+       by default.  Both faces of an axis are periodic or neither. */
+    int32_t bc[6];
+    int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL needs
+                                   path = EMMA_RT_PATH_REFERENCE and no adjoint */
+    int32_t reserved;           /* 0 */
+    double inflow[6];           /* photons cm^-2 s^-1 through each INFLOW face, >= 0 */
 } emma_rt_config;
 
 typedef struct {
@@ -128,7 +154,8 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
  *   g_nH            device double [cells], dL/dn_H is ADDED to it
  *   g_src_rate      device double [n_src], dL/d(src_rate) is ADDED to it
  * The segment is recomputed forward from (N0, F0, x0, T0) into the context's
- * tape.  Returns OK, EINVAL or EHIP. */
+ * tape.  Every boundary kind is differentiated (an inflow face's beam is a
+ * constant); the HLL flux is not (EINVAL).  Returns OK, EINVAL or EHIP. */
 int emma_rt_step_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
                          const double *x0, const double *T0, const double *n_H,
                          const int64_t *src_cell, const double *src_rate, int32_t n_src,

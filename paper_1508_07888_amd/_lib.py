@@ -23,6 +23,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESUBSTEP",
 EMMA_RT_FP64 = 0
 EMMA_RT_MIXED = 1
 PATHS = {"fused": 0, "split": 1, "reference": 2}
+BCS = {"periodic": 0, "transmissive": 1, "reflective": 2, "inflow": 3}
+FLUXES = {"glf": 0, "hll": 1}
 
 EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_adjoint", "emma_rt_free",
            "emma_rt_last_error", "emma_rt_group_constants", "emma_rt_scratch_bytes",
@@ -39,6 +41,8 @@ class emma_rt_config(ctypes.Structure):
         ("path", ctypes.c_int32),
         ("sigma_N", ctypes.c_double * MAX_GROUPS), ("sigma_E", ctypes.c_double * MAX_GROUPS),
         ("mean_E", ctypes.c_double * MAX_GROUPS), ("src_frac", ctypes.c_double * MAX_GROUPS),
+        ("bc", ctypes.c_int32 * 6), ("flux", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("inflow", ctypes.c_double * 6),
     ]
 
 

@@ -383,61 +383,84 @@ __global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, cons
 }
 
 // ------------------------------------------------------- transport adjoint
-// Closure derivatives of P = a I + bq F F^T (a = (1-chi)/2 N, bq = (3chi-1)/2 N/|F|^2,
-// chi(q), q = |F|^2/(c N)^2 clipped at 1):  da/dN, da/dF = ga F, bq,
-// dbq/dN, dbq/dF = gb F.
+// Closure derivatives in terms of the reduced flux g = F/(c N), q = |g|^2:
+// P = a I + N K g g^T with a = (1 - chi)/2 N and K = h(q) below the clip,
+// 1/q at it (chi = 1).  Then
+//   dP/dN   = aN I + KN g g^T,
+//   dP/dF_k = (1/c) [GA g_k I + GB g_k g g^T + K (e_k g^T + g e_k^T)],
+// with only O(1) factors, so faint fields (|F|^2 or N^-4 out of range) are safe.
+// Below the clip, with (3 chi - 1)/2 = q h, chi' = dchi/dq = 2 (h + q h')/3:
+//   aN = (1 - chi)/2 + q chi',  KN = -(h + 2 q h'),  GA = -chi',  GB = 2 h';
+// at the clip aN = GA = 0, KN = 1/q, GB = -2/q^2.
 struct ClosureJac {
-    double aN, ga, bq, bqN, gb;
+    double aN, GA, K, KN, GB;
+    double g[3];
 };
 
 __host__ __device__ __forceinline__ ClosureJac closure_jac(double N, double Fx, double Fy, double Fz, double c) {
-    ClosureJac j{1.0 / 3.0, 0.0, 0.0, 0.0, 0.0};
-    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    if (!(N > 0.0) || !(F2 > 0.0)) return j;  // P = N/3 I: only dP/dN = I/3
+    ClosureJac j{1.0 / 3.0, 0.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
+    if (!(N > 0.0)) return j;  // P = N/3 I: only dP/dN = I/3
     const double icn = 1.0 / (c * N);
-    double q = F2 * icn * icn;
-    double dchi = 0.0;
+    j.g[0] = Fx * icn;
+    j.g[1] = Fy * icn;
+    j.g[2] = Fz * icn;
+    const double q = j.g[0] * j.g[0] + j.g[1] * j.g[1] + j.g[2] * j.g[2];
     if (q >= 1.0) {
-        q = 1.0;
-    } else {
-        const double s = sqrt(4.0 - 3.0 * q);
-        const double den = 5.0 + 2.0 * s;
-        dchi = (4.0 * den + 3.0 * (3.0 + 4.0 * q) / s) / (den * den);
+        j.aN = 0.0;
+        j.K = 1.0 / q;
+        j.KN = 1.0 / q;
+        j.GB = -2.0 / (q * q);
+        return j;
     }
     const double s = sqrt(4.0 - 3.0 * q);
-    const double chi = (3.0 + 4.0 * q) / (5.0 + 2.0 * s);
-    const double B = 0.5 * (3.0 * chi - 1.0) * N;
+    const double den = 5.0 + 2.0 * s, t = 2.0 + s;
+    const double h = (6.0 + 3.0 / t) / den;
+    const double hp = (1.5 / s) * (3.0 / (t * t * den) + 2.0 * (6.0 + 3.0 / t) / (den * den));
+    const double chi = (1.0 + 2.0 * q * h) / 3.0;
+    const double dchi = 2.0 * (h + q * hp) / 3.0;
     j.aN = 0.5 * (1.0 - chi) + dchi * q;
-    j.ga = -dchi * icn * icn * N;  // -chi' / (c^2 N)
-    j.bq = B / F2;
-    j.bqN = (0.5 * (3.0 * chi - 1.0) - 3.0 * dchi * q) / F2;
-    j.gb = 3.0 * dchi * icn * icn * N / F2 - 2.0 * B / (F2 * F2);
+    j.GA = -dchi;
+    j.K = h;
+    j.KN = -(h + 2.0 * q * hp);
+    j.GB = 2.0 * hp;
     return j;
 }
 
+// M_d(U)^T v for the flux Jacobian M_d = dFt_d/dU, Ft_d = (F_d, c^2 P_.d), of
+// a state with closure Jacobian J; v = (v_N, w).
+__host__ __device__ __forceinline__ void flux_jac_t(const ClosureJac &J, int d, double c, const double v[4],
+                                                    double out[4]) {
+    const double *g = J.g;
+    const double w[3] = {v[1], v[2], v[3]};
+    const double wg = w[0] * g[0] + w[1] * g[1] + w[2] * g[2];
+    out[0] = c * c * (J.aN * w[d] + J.KN * wg * g[d]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double mk = c * (J.GA * g[k] * w[d] + J.GB * g[k] * wg * g[d] + J.K * w[k] * g[d]);
+        if (k == d) mk += v[0] + c * J.K * wg;
+        out[1 + k] = mk;
+    }
+}
+
+// Transpose of the transport step.  U_i enters U*_{i+e_d} through A_d(U_i)
+// and U*_{i-e_d} through B_d(U_i) (A = (Ft + c U)/2, B = (c U - Ft)/2), and
+// U*_i through -c U_i per axis; at a non-periodic face, cell i also sees the
+// ghost of itself (A_d(ghost) across its minus face, B_d(ghost) across its
+// plus face): ghost = U_i (transmissive), U_i with F_d reversed (reflective,
+// a symmetric map R, so the term is R A'(R U)^T g_i) or a constant (inflow).
 template <int G, typename S>
 __global__ __launch_bounds__(256) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
                                                        const double *__restrict__ gU, S *__restrict__ gN,
-                                                       S *__restrict__ gF, Grid gr, double c, double lam) {
+                                                       S *__restrict__ gF, Grid gr, double c, double lam,
+                                                       Bounds<S> bnd) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= gr.V) return;
     const int64_t V = gr.V;
     const int x = (int)(i % gr.nx);
     const int y = (int)((i / gr.nx) % gr.ny);
     const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
-    int64_t nb[3][2];
-    {
-        const int xm = x == 0 ? gr.nx - 1 : x - 1, xp = x == gr.nx - 1 ? 0 : x + 1;
-        const int ym = y == 0 ? gr.ny - 1 : y - 1, yp = y == gr.ny - 1 ? 0 : y + 1;
-        const int zm = z == 0 ? gr.nz - 1 : z - 1, zp = z == gr.nz - 1 ? 0 : z + 1;
-        const int64_t row = gr.nx, pl = (int64_t)gr.nx * gr.ny;
-        nb[0][0] = i - x + xm;
-        nb[0][1] = i - x + xp;
-        nb[1][0] = i + (int64_t)(ym - y) * row;
-        nb[1][1] = i + (int64_t)(yp - y) * row;
-        nb[2][0] = i + (int64_t)(zm - z) * pl;
-        nb[2][1] = i + (int64_t)(zp - z) * pl;
-    }
+    const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
+    const double hl = 0.5 * lam;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const double n = (double)N[(int64_t)g * V + i];
@@ -445,30 +468,43 @@ __global__ __launch_bounds__(256) void k_transport_adj(const S *__restrict__ N, 
                               (double)F[((int64_t)g * 3 + 2) * V + i]};
         const ClosureJac J = closure_jac(n, Fv[0], Fv[1], Fv[2], c);
         const double *gUg = gU + (int64_t)(4 * g) * V;
-        double out[4];
+        double gi[4], out[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = (1.0 - 3.0 * c * lam) * gUg[(int64_t)q * V + i];
-        const double cc = c * c;
+        for (int q = 0; q < 4; ++q) {
+            gi[q] = gUg[(int64_t)q * V + i];
+            out[q] = (1.0 - 3.0 * c * lam) * gi[q];
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double vp[4], vm[4];
+            // ordinary neighbours: (lam/2) [c (v+ + v-) + M_d(U)^T (v+ - v-)]
+            double vp[4], vm[4], dv[4], m[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                vp[q] = gUg[(int64_t)q * V + nb[d][1]];
-                vm[q] = gUg[(int64_t)q * V + nb[d][0]];
-                out[q] += 0.5 * lam * c * (vp[q] + vm[q]);
+                vp[q] = nb.face[d][1] < 0 ? gUg[(int64_t)q * V + nb.idx[d][1]] : 0.0;
+                vm[q] = nb.face[d][0] < 0 ? gUg[(int64_t)q * V + nb.idx[d][0]] : 0.0;
+                dv[q] = vp[q] - vm[q];
             }
-            // (lam/2) M_d(U)^T (v+ - v-),  M_d = dFt_d/dU,  Ft_d = (F_d, c^2 P_.d)
-            const double vN = vp[0] - vm[0];
-            const double w[3] = {vp[1] - vm[1], vp[2] - vm[2], vp[3] - vm[3]};
-            const double wF = w[0] * Fv[0] + w[1] * Fv[1] + w[2] * Fv[2];
-            const double mN = cc * (J.aN * w[d] + J.bqN * wF * Fv[d]);
-            out[0] += 0.5 * lam * mN;
+            flux_jac_t(J, d, c, dv, m);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                double mk = cc * (J.ga * Fv[k] * w[d] + J.gb * Fv[k] * wF * Fv[d] + J.bq * w[k] * Fv[d]);
-                if (k == d) mk += vN + cc * J.bq * wF;
-                out[1 + k] += 0.5 * lam * mk;
+            for (int q = 0; q < 4; ++q) out[q] += hl * (c * (vp[q] + vm[q]) + m[q]);
+            // ghosts of this cell across its own non-periodic faces
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int face = nb.face[d][s];
+                if (face < 0 || bnd.kind[face] == BC_INFLOW) continue;
+                const bool refl = bnd.kind[face] == BC_REFLECTIVE;
+                double Fg[3] = {Fv[0], Fv[1], Fv[2]};
+                if (refl) Fg[d] = -Fg[d];
+                const ClosureJac Jg = closure_jac(n, Fg[0], Fg[1], Fg[2], c);
+                double mg[4];
+                flux_jac_t(Jg, d, c, gi, mg);
+                const double sg = s ? -1.0 : 1.0;  // A across the minus face, B across the plus face
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double t = hl * (c * gi[q] + sg * mg[q]);
+                    if (refl && q == 1 + d) t = -t;
+                    out[q] += t;
+                }
             }
         }
         gN[(int64_t)g * V + i] = (S)out[0];

@@ -41,6 +41,8 @@ struct emma_rt_ctx {
     uint32_t *work_cells;        // [V]
     int list_blocks;             // grid of the second chemistry pass
     AdjointScratch adj;
+    Bounds<float> bnd_f;   // global boundaries in the storage precision
+    Bounds<double> bnd_d;
     // kernel timing (emma_rt_profile_enable)
     int prof;
     std::vector<hipEvent_t> *ev;     // pool, pairs (start, stop)
@@ -121,6 +123,20 @@ static GroupConsts group_consts(const emma_rt_config &cfg) {
     return gc;
 }
 
+template <typename S> static const Bounds<S> &bounds_of(const emma_rt_ctx *c);
+template <> const Bounds<float> &bounds_of<float>(const emma_rt_ctx *c) { return c->bnd_f; }
+template <> const Bounds<double> &bounds_of<double>(const emma_rt_ctx *c) { return c->bnd_d; }
+
+template <typename S> static Bounds<S> make_bounds(const emma_rt_config &cfg) {
+    Bounds<S> b;
+    for (int f = 0; f < 6; ++f) {
+        b.kind[f] = cfg.bc[f];
+        for (int g = 0; g < EMMA_RT_MAX_GROUPS; ++g)
+            b.phi[f][g] = (S)(cfg.bc[f] == BC_INFLOW && g < cfg.n_groups ? cfg.inflow[f] * cfg.src_frac[g] : 0.0);
+    }
+    return b;
+}
+
 static const char *config_error(const emma_rt_config *cfg) {
     if (!cfg) return "config is NULL";
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return "grid dimensions must be >= 1";
@@ -132,6 +148,20 @@ static const char *config_error(const emma_rt_config *cfg) {
     if (cfg->max_substeps < 1) return "max_substeps must be >= 1";
     if (cfg->adjoint_max_steps < 0) return "adjoint_max_steps must be >= 0";
     if (cfg->path < EMMA_RT_PATH_FUSED || cfg->path > EMMA_RT_PATH_REFERENCE) return "bad path";
+    for (int d = 0; d < 3; ++d) {
+        const int a = cfg->bc[2 * d], b = cfg->bc[2 * d + 1];
+        if (a < EMMA_RT_BC_PERIODIC || a > EMMA_RT_BC_INFLOW || b < EMMA_RT_BC_PERIODIC || b > EMMA_RT_BC_INFLOW)
+            return "bc values must be emma_rt_bc kinds (0..3)";
+        if ((a == EMMA_RT_BC_PERIODIC) != (b == EMMA_RT_BC_PERIODIC))
+            return "both faces of an axis must be periodic or neither";
+    }
+    for (int f = 0; f < 6; ++f)
+        if (!(cfg->inflow[f] >= 0) || !isfinite(cfg->inflow[f])) return "inflow must be finite and >= 0";
+    if (cfg->flux != EMMA_RT_FLUX_GLF && cfg->flux != EMMA_RT_FLUX_HLL) return "bad flux";
+    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->path != EMMA_RT_PATH_REFERENCE)
+        return "the HLL flux runs on the reference path only (path = EMMA_RT_PATH_REFERENCE)";
+    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->adjoint_max_steps > 0)
+        return "the adjoint differentiates the GLF flux only (adjoint_max_steps must be 0 with HLL)";
     if (cfg->path != EMMA_RT_PATH_REFERENCE &&
         !tiled_supported(Grid{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz}))
         return "grid too large for the tiled kernels (V * 8 bytes >= 4 GiB): use the reference path";
@@ -199,6 +229,8 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
     c->grid.nz = cfg->nz;
     c->grid.V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     c->elem = cfg->precision == EMMA_RT_FP64 ? 8 : 4;
+    c->bnd_f = make_bounds<float>(*cfg);
+    c->bnd_d = make_bounds<double>(*cfg);
     (void)hipGetDevice(&c->device);
     const int64_t V = c->grid.V;
     const int G = cfg->n_groups;
@@ -324,7 +356,7 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
             {
                 Timed t(c, KID_FUSED);
                 e = launch_fused<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
-                                             dt / c->cfg.dx, c->cnt, wl);
+                                             dt / c->cfg.dx, c->cnt, wl, bounds_of<S>(c));
             }
             if (e) return fail(c, EMMA_RT_EHIP, "fused kernel launch failed: %s",
                                hipGetErrorString(hipGetLastError()));
@@ -340,11 +372,16 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
     for (int s = 0; s < n_steps; ++s) {
         if (c->cfg.path == EMMA_RT_PATH_SPLIT) {
             Timed t(c, KID_TRANSPORT);
-            launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt);
+            launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
+                                               bounds_of<S>(c));
+        } else if (c->cfg.flux == EMMA_RT_FLUX_HLL) {
+            Timed t(c, KID_TRANSPORT);
+            hipLaunchKernelGGL((k_transport<G, S, DIAG, false, true>), dim3(nblk), dim3(tb), 0, c->stream, N, F,
+                               Ns, Fs, gr, cr, lam, c->cnt, bounds_of<S>(c));
         } else {
             Timed t(c, KID_TRANSPORT);
             hipLaunchKernelGGL((k_transport<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, N, F, Ns,
-                               Fs, gr, cr, lam, c->cnt);
+                               Fs, gr, cr, lam, c->cnt, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport")) return e;
         if (int e = reset_worklist(c)) return e;
@@ -503,7 +540,7 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
         {
             Timed t(c, KID_ADJ_FWD);
             hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
-                               Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt);
+                               Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport (adjoint recompute)")) return e;
         {
@@ -519,7 +556,7 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
         {
             Timed t(c, KID_ADJ_TRANSPORT);
             hipLaunchKernelGGL((k_transport_adj<G, S>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
-                               c->adj.gU, gN, gF, gr, c->cfg.c_red, lam);
+                               c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport_adj")) return e;
     }

@@ -7,9 +7,10 @@
 // so the conservative update of eq. (e:uprt), 3D unsplit, is
 //   U* = U + (dt/dx) [ sum_d A_d(U_{i-e_d}) + B_d(U_{i+e_d}) - 3 c U_i ].
 // Each cell's closure P(U) is computed once per step by the thread that owns
-// its column (halo cells once more by the block that needs them); x/y
-// neighbours are exchanged through LDS, z neighbours stay in registers while
-// the block marches up its column chunk.
+// its column (halo cells once more by the block that needs them), and the
+// owner publishes the four x/y split vectors 2A_x, 2B_x, 2A_y, 2B_y in LDS:
+// each neighbour then reads exactly the one 4-vector it needs.  z neighbours
+// stay in registers while the block marches up its column chunk.
 //
 // Block: 64 x 4 threads own a 64 x 4 column tile and march over LZ planes.
 // Blocks are numbered so that each XCD (blocks are dealt round-robin to the 8
@@ -27,9 +28,24 @@
 namespace emma {
 
 constexpr int kTX = 64;
-constexpr int kTY = 4;
-constexpr int kLX = kTX + 2;
-constexpr int kLY = kTY + 2;
+// Tile heights (rows of 64 cells per block) and the longest z chunk; tuning
+// knobs, measured on the device.
+#ifndef EMMA_TY_SPLIT
+#define EMMA_TY_SPLIT 4
+#endif
+#ifndef EMMA_TY_FUSED
+#define EMMA_TY_FUSED 4
+#endif
+#ifndef EMMA_LZ_MAX
+#define EMMA_LZ_MAX 32
+#endif
+// prefetch depth of the z march (planes loaded ahead of use)
+#ifndef EMMA_PD_SPLIT
+#define EMMA_PD_SPLIT 4
+#endif
+#ifndef EMMA_PD_FUSED
+#define EMMA_PD_FUSED 0
+#endif
 
 template <typename R> struct TileArgs {
     const R *N, *F;
@@ -44,6 +60,7 @@ template <typename R> struct TileArgs {
     ChemParams cp;
     unsigned long long *cnt;
     WorkList wl;
+    Bounds<R> bnd;
 };
 
 // Physical tile of block b when the hardware deals blocks to 8 XCDs
@@ -79,6 +96,26 @@ __device__ __forceinline__ void load_cell(const R *__restrict__ N, const R *__re
     }
 }
 
+// Ghost of a boundary cell's state across a non-periodic face.
+template <typename R>
+__device__ __forceinline__ Vec4<R> ghost4(const Bounds<R> &b, int face, int g, R c, Vec4<R> u) {
+    R f[3] = {u.fx, u.fy, u.fz};
+    ghost(b, face, g, c, u.n, f);
+    return Vec4<R>{u.n, f[0], f[1], f[2]};
+}
+
+// The four x/y split vectors (times 2) of one state with its closure.
+template <typename R>
+__device__ __forceinline__ void split_xy(const Vec4<R> &u, const R P[6], R c, Vec4<R> &Ax, Vec4<R> &Bx,
+                                         Vec4<R> &Ay, Vec4<R> &By) {
+    const R cN = c * u.n, cFx = c * u.fx, cFy = c * u.fy, cFz = c * u.fz, cc = c * c;
+    const R pxx = cc * P[0], pxy = cc * P[1], pxz = cc * P[2], pyy = cc * P[3], pyz = cc * P[4];
+    Ax = Vec4<R>{u.fx + cN, pxx + cFx, pxy + cFy, pxz + cFz};
+    Bx = Vec4<R>{cN - u.fx, cFx - pxx, cFy - pxy, cFz - pxz};
+    Ay = Vec4<R>{u.fy + cN, pxy + cFx, pyy + cFy, pyz + cFz};
+    By = Vec4<R>{cN - u.fy, cFx - pxy, cFy - pyy, cFz - pyz};
+}
+
 // A_z and B_z parts (times 2) of one state with its closure.
 template <typename R>
 __device__ __forceinline__ Vec4<R> az2(const Vec4<R> &u, const R P[6], R c) {
@@ -89,12 +126,18 @@ __device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R P[6], R c) {
     return Vec4<R>{c * u.n - u.fz, c * u.fx - c * c * P[2], c * u.fy - c * c * P[4], c * u.fz - c * c * P[5]};
 }
 
-template <int G, typename R, bool DIAG, bool FUSE, bool FAST>
-__global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
-    // plane z of the current group: state, (Pxx, Pxy, Pxz, Pyy) and Pyz, double-buffered
-    __shared__ Vec4<R> ldsU[2][kLY][kLX];
-    __shared__ Vec4<R> ldsP[2][kLY][kLX];
-    __shared__ R ldsQ[2][kLY][kLX];
+// FULL: every tile is a whole 64 x TY tile (nx % 64 == 0, ny % TY == 0), so
+// every thread owns a cell and no store needs a predicate.
+template <int G, typename R, bool DIAG, bool FUSE, bool FAST, int TY, int PD, bool FULL>
+__global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_tiled(TileArgs<R> a) {
+    // plane z of the current group, double-buffered: only the split vectors a
+    // neighbour reads.  Consumer (ty, tx) reads lAx[ty][tx] (left cell's A_x),
+    // lBx[ty][tx + 1] (right cell's B_x), lAy[ty][tx] (A_y of the cell below),
+    // lBy[ty][tx] (B_y of the cell above).
+    __shared__ Vec4<R> lAx[2][TY][kTX + 1];
+    __shared__ Vec4<R> lBx[2][TY][kTX + 1];
+    __shared__ Vec4<R> lAy[2][TY + 1][kTX];
+    __shared__ Vec4<R> lBy[2][TY][kTX];
     const int tid = threadIdx.x;
     const int tx = tid & (kTX - 1), ty = tid >> 6;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -102,72 +145,132 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
     const int nx = a.gr.nx, ny = a.gr.ny, nz = a.gr.nz;
     const int64_t V = a.gr.V;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const int x0 = tile_x * kTX, y0 = tile_y * kTY, z0 = tile_z * a.LZ;
+    const int x0 = tile_x * kTX, y0 = tile_y * TY, z0 = tile_z * a.LZ;
     const int z1 = min(z0 + a.LZ, nz);
-    const int w = min(kTX, nx - x0), h = min(kTY, ny - y0);
-    const bool active = tx < w && ty < h;
+    const int w = min(kTX, nx - x0), h = min(TY, ny - y0);
+    const bool active = FULL || (tx < w && ty < h);
     const uint32_t col = active ? (uint32_t)(y0 + ty) * nx + (x0 + tx) : 0u;  // cell within a plane
     constexpr uint32_t E = sizeof(R);
 
-    // halo role: bottom row, top row, left column, right column of the tile
-    int hrole = -1, hlx = 0, hly = 0;
+    // halo role: bottom row, top row, left column, right column of the tile;
+    // across a non-periodic face the halo cell is the boundary cell itself and
+    // hface names the face whose ghost it becomes
+    const Bounds<R> &bd = a.bnd;
+    int hrole = -1, hlx = 0, hly = 0, hface = -1;
     uint32_t hcol = 0;
     if (tid < kTX) {
-        if (tid < w) { hrole = 0; hlx = tid + 1; hly = 0; hcol = (uint32_t)((y0 + ny - 1) % ny) * nx + x0 + tid; }
+        if (tid < w) {
+            hrole = 0; hlx = tid + 1; hly = 0;
+            int yy = y0 - 1;
+            if (yy < 0) {
+                if (bd.kind[2] == BC_PERIODIC) yy = ny - 1;
+                else { yy = 0; hface = 2; }
+            }
+            hcol = (uint32_t)yy * nx + x0 + tid;
+        }
     } else if (tid < 2 * kTX) {
         const int cx = tid - kTX;
-        if (cx < w) { hrole = 1; hlx = cx + 1; hly = h + 1; hcol = (uint32_t)((y0 + h) % ny) * nx + x0 + cx; }
-    } else if (tid < 2 * kTX + kTY) {
+        if (cx < w) {
+            hrole = 1; hlx = cx + 1; hly = h + 1;
+            int yy = y0 + h;
+            if (yy >= ny) {
+                if (bd.kind[3] == BC_PERIODIC) yy = 0;
+                else { yy = ny - 1; hface = 3; }
+            }
+            hcol = (uint32_t)yy * nx + x0 + cx;
+        }
+    } else if (tid < 2 * kTX + TY) {
         const int cy = tid - 2 * kTX;
-        if (cy < h) { hrole = 2; hlx = 0; hly = cy + 1; hcol = (uint32_t)(y0 + cy) * nx + (x0 + nx - 1) % nx; }
-    } else if (tid < 2 * kTX + 2 * kTY) {
-        const int cy = tid - 2 * kTX - kTY;
-        if (cy < h) { hrole = 3; hlx = w + 1; hly = cy + 1; hcol = (uint32_t)(y0 + cy) * nx + (x0 + w) % nx; }
+        if (cy < h) {
+            hrole = 2; hlx = 0; hly = cy + 1;
+            int xx = x0 - 1;
+            if (xx < 0) {
+                if (bd.kind[0] == BC_PERIODIC) xx = nx - 1;
+                else { xx = 0; hface = 0; }
+            }
+            hcol = (uint32_t)(y0 + cy) * nx + xx;
+        }
+    } else if (tid < 2 * kTX + 2 * TY) {
+        const int cy = tid - 2 * kTX - TY;
+        if (cy < h) {
+            hrole = 3; hlx = w + 1; hly = cy + 1;
+            int xx = x0 + w;
+            if (xx >= nx) {
+                if (bd.kind[1] == BC_PERIODIC) xx = 0;
+                else { xx = nx - 1; hface = 1; }
+            }
+            hcol = (uint32_t)(y0 + cy) * nx + xx;
+        }
     }
+    // z faces: ghosts of plane 0 below the grid and of plane nz-1 above it
+    const bool zlo_ghost = bd.kind[4] != BC_PERIODIC, zhi_ghost = bd.kind[5] != BC_PERIODIC;
 
     const R c = a.c, half = R(0.5);
-    // rolling column window: cur = plane z, nxt = plane z+1, Az2 = 2 A_z(plane z-1)
-    Vec4<R> cur[G], nxt[G], nn[G], hal[G], hnext[G], Az2[G];
+    // The z march keeps a window of U = PD + 2 planes of the own column in
+    // registers, W[(z - z0) mod U] = plane z, and of the halo column, H[...]:
+    // the planes z and z+1 in use and PD planes in flight.  The loop is
+    // unrolled by U so every slot is a fixed register set (no copies), and
+    // every global load is issued unconditionally (planes past the chunk are
+    // clamped to its last plane, threads without a halo cell load their own
+    // column) so the compiler can wait for exactly the plane it needs instead
+    // of draining all loads in flight.
+    constexpr int U = PD + 2;
+    Vec4<R> W[U][G], H[U][G], Az2[G], Bz2[G];
     R Pc[G][6], Pn[G][6];
     int64_t nlim = 0, nneg = 0;
     ChemStats tot{0, 0, 0, 0};
     int maxsub = 0;
+    // the halo cell's ghost, read once (a face index into the argument block
+    // would otherwise be a memory load inside the loop)
+    int hkind = BC_PERIODIC, hd = 0;
+    R hsgn = R(1), hphi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) hphi[g] = R(0);
+    if (hface >= 0) {
+        hkind = bd.kind[hface];
+        hd = hface >> 1;
+        hsgn = (hface & 1) ? R(-1) : R(1);
+#pragma unroll
+        for (int g = 0; g < G; ++g) hphi[g] = bd.phi[hface][g];
+    }
+    const uint32_t hsrc = hrole >= 0 ? hcol : col;  // threads without a halo cell reload their own
 
     auto zwrap = [nz](int z) { return (uint32_t)((z % nz + nz) % nz); };
     {
-        const Vec4<R> zero{R(0), R(0), R(0), R(0)};
-#pragma unroll
-        for (int g = 0; g < G; ++g) { cur[g] = zero; nxt[g] = zero; hal[g] = zero; }
         Vec4<R> um[G];
+        load_cell<G>(a.N, a.F, V, (zwrap(z0 - 1) * plane + col) * E, um);
 #pragma unroll
-        for (int g = 0; g < G; ++g) um[g] = zero;
-        if (active) {
-            load_cell<G>(a.N, a.F, V, (zwrap(z0 - 1) * plane + col) * E, um);
-            load_cell<G>(a.N, a.F, V, ((uint32_t)z0 * plane + col) * E, cur);
-            load_cell<G>(a.N, a.F, V, (zwrap(z0 + 1) * plane + col) * E, nxt);
-        }
-        if (hrole >= 0) load_cell<G>(a.N, a.F, V, ((uint32_t)z0 * plane + hcol) * E, hal);
+        for (int k = 0; k < U; ++k) load_cell<G>(a.N, a.F, V, (zwrap(min(z0 + k, z1)) * plane + col) * E, W[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            load_cell<G>(a.N, a.F, V, ((uint32_t)min(z0 + k, z1 - 1) * plane + hsrc) * E, H[k]);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
+            if (z0 == 0 && zlo_ghost) um[g] = ghost4(bd, 4, g, c, W[0][g]);
+            if (z0 + 1 == nz && zhi_ghost) W[1][g] = ghost4(bd, 5, g, c, W[0][g]);
             R Pm[6];
             m1_pressure(um[g].n, um[g].fx, um[g].fy, um[g].fz, c, Pm);
             Az2[g] = az2(um[g], Pm, c);
-            m1_pressure(cur[g].n, cur[g].fx, cur[g].fy, cur[g].fz, c, Pc[g]);
-            m1_pressure(nxt[g].n, nxt[g].fx, nxt[g].fy, nxt[g].fz, c, Pn[g]);
+            m1_pressure(W[0][g].n, W[0][g].fx, W[0][g].fy, W[0][g].fz, c, Pc[g]);
+            m1_pressure(W[1][g].n, W[1][g].fx, W[1][g].fy, W[1][g].fz, c, Pn[g]);
+            Bz2[g] = bz2(W[1][g], Pn[g], c);
         }
     }
 
     int buf = 0;
-    for (int z = z0; z < z1; ++z) {
-        // prefetch: own column two planes up, halo one plane up, gas state of plane z
+    // plane z: transport of every group, optional chemistry, store; then
+    // refill the freed slots with plane z + U and prepare plane z + 2's closure
+    auto plane_step = [&](const int z, Vec4<R>(&cur)[G], Vec4<R>(&nxt)[G], Vec4<R>(&nn)[G], Vec4<R>(&hal)[G]) {
         const uint32_t zc = (uint32_t)z * plane + col;
-        if (active) load_cell<G>(a.N, a.F, V, (zwrap(z + 2) * plane + col) * E, nn);
-        if (hrole >= 0 && z + 1 < z1) load_cell<G>(a.N, a.F, V, ((uint32_t)(z + 1) * plane + hcol) * E, hnext);
         double xg = 0.0, Tg = 0.0, n0g = 0.0;
-        if (FUSE && active) {
+        if (FUSE) {
             xg = ld(a.x, zc * 8u);
             Tg = ld(a.T, zc * 8u);
             n0g = ld(a.n0, zc * 8u);
+            // the fused kernel recomputes plane z's closure rather than keeping
+            // it live through the chemistry (registers, not ALU, limit it)
+#pragma unroll
+            for (int g = 0; g < G; ++g) m1_pressure(cur[g].n, cur[g].fx, cur[g].fy, cur[g].fz, c, Pc[g]);
         }
 
         Vec4<R> us[G];
@@ -175,99 +278,103 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
         for (int g = 0; g < G; ++g) {
             // publish plane z of group g: own cell and halo cell
             if (active) {
-                ldsU[buf][ty + 1][tx + 1] = cur[g];
-                ldsP[buf][ty + 1][tx + 1] = Vec4<R>{Pc[g][0], Pc[g][1], Pc[g][2], Pc[g][3]};
-                ldsQ[buf][ty + 1][tx + 1] = Pc[g][4];
+                Vec4<R> Ax, Bx, Ay, By;
+                split_xy(cur[g], Pc[g], c, Ax, Bx, Ay, By);
+                lAx[buf][ty][tx + 1] = Ax;
+                lBx[buf][ty][tx] = Bx;
+                lAy[buf][ty + 1][tx] = Ay;
+                if (ty > 0) lBy[buf][ty - 1][tx] = By;
             }
             if (hrole >= 0) {
+                Vec4<R> hv = hal[g];
+                if (hkind == BC_REFLECTIVE) {
+                    if (hd == 0) hv.fx = -hv.fx;
+                    else if (hd == 1) hv.fy = -hv.fy;
+                    else hv.fz = -hv.fz;
+                } else if (hkind == BC_INFLOW) {  // beam into the domain across the face
+                    hv.n = hphi[g] / c;
+                    hv.fx = hd == 0 ? hsgn * hphi[g] : R(0);
+                    hv.fy = hd == 1 ? hsgn * hphi[g] : R(0);
+                    hv.fz = hd == 2 ? hsgn * hphi[g] : R(0);
+                }
                 R Ph[6];
-                m1_pressure(hal[g].n, hal[g].fx, hal[g].fy, hal[g].fz, c, Ph);
-                ldsU[buf][hly][hlx] = hal[g];
-                ldsP[buf][hly][hlx] = Vec4<R>{Ph[0], Ph[1], Ph[2], Ph[3]};
-                ldsQ[buf][hly][hlx] = Ph[4];
+                m1_pressure(hv.n, hv.fx, hv.fy, hv.fz, c, Ph);
+                Vec4<R> Ax, Bx, Ay, By;
+                split_xy(hv, Ph, c, Ax, Bx, Ay, By);
+                if (hrole == 0) lAy[buf][0][hlx - 1] = Ay;            // row below the tile
+                else if (hrole == 1) lBy[buf][h - 1][hlx - 1] = By;   // row above
+                else if (hrole == 2) lAx[buf][hly - 1][0] = Ax;       // column left
+                else lBx[buf][hly - 1][w] = Bx;                       // column right
             }
             __syncthreads();
-            if (active) {
-                const int lx = tx + 1, ly = ty + 1;
-                const R cc = c * c;
-                // 2 x (A_x of the left, B_x of the right, A_y below, B_y above)
-                const Vec4<R> uL = ldsU[buf][ly][lx - 1], pL = ldsP[buf][ly][lx - 1];
-                const Vec4<R> uR = ldsU[buf][ly][lx + 1], pR = ldsP[buf][ly][lx + 1];
-                const Vec4<R> uD = ldsU[buf][ly - 1][lx], pD = ldsP[buf][ly - 1][lx];
-                const Vec4<R> uT = ldsU[buf][ly + 1][lx], pT = ldsP[buf][ly + 1][lx];
-                const R qD = ldsQ[buf][ly - 1][lx], qT = ldsQ[buf][ly + 1][lx];
-                // ldsP holds (Pxx, Pxy, Pxz, Pyy) in (n, fx, fy, fz)
-                R sN = (uL.fx + c * uL.n) + (c * uR.n - uR.fx) + (uD.fy + c * uD.n) + (c * uT.n - uT.fy);
-                R sX = (cc * pL.n + c * uL.fx) + (c * uR.fx - cc * pR.n) + (cc * pD.fx + c * uD.fx) +
-                       (c * uT.fx - cc * pT.fx);
-                R sY = (cc * pL.fx + c * uL.fy) + (c * uR.fy - cc * pR.fx) + (cc * pD.fz + c * uD.fy) +
-                       (c * uT.fy - cc * pT.fz);
-                R sZ = (cc * pL.fy + c * uL.fz) + (c * uR.fz - cc * pR.fy) + (cc * qD + c * uD.fz) +
-                       (c * uT.fz - cc * qT);
-                // z: 2 A_z of plane z-1 (kept from the last iteration), 2 B_z of plane z+1
-                const Vec4<R> bz = bz2(nxt[g], Pn[g], c);
-                const R three_c = R(3) * c;
-                R n = cur[g].n + a.lam * (half * (sN + Az2[g].n + bz.n) - three_c * cur[g].n);
-                R fx = cur[g].fx + a.lam * (half * (sX + Az2[g].fx + bz.fx) - three_c * cur[g].fx);
-                R fy = cur[g].fy + a.lam * (half * (sY + Az2[g].fy + bz.fy) - three_c * cur[g].fy);
-                R fz = cur[g].fz + a.lam * (half * (sZ + Az2[g].fz + bz.fz) - three_c * cur[g].fz);
-                if (n < R(0)) { n = R(0); nneg++; }
+            {
+                const Vec4<R> aL = lAx[buf][ty][tx], bR = lBx[buf][ty][tx + 1];
+                const Vec4<R> aD = lAy[buf][ty][tx], bT = lBy[buf][ty][tx];
+                // sum of the six split vectors (times 2) minus 6 c U, times lam / 2
+                const R s6 = R(6) * c;
+                const R hl = half * a.lam;
+                R n = cur[g].n + hl * ((aL.n + bR.n) + (aD.n + bT.n) + (Az2[g].n + Bz2[g].n) - s6 * cur[g].n);
+                R fx = cur[g].fx + hl * ((aL.fx + bR.fx) + (aD.fx + bT.fx) + (Az2[g].fx + Bz2[g].fx) - s6 * cur[g].fx);
+                R fy = cur[g].fy + hl * ((aL.fy + bR.fy) + (aD.fy + bT.fy) + (Az2[g].fy + Bz2[g].fy) - s6 * cur[g].fy);
+                R fz = cur[g].fz + hl * ((aL.fz + bR.fz) + (aD.fz + bT.fz) + (Az2[g].fz + Bz2[g].fz) - s6 * cur[g].fz);
+                if (n < R(0)) { n = R(0); if (active) nneg++; }
                 const R F2 = fx * fx + fy * fy + fz * fz;
                 const R cn = c * n;
                 if (F2 > cn * cn) {
-                    const R s = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
-                    fx *= s; fy *= s; fz *= s;
-                    nlim++;
+                    const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
+                    fx *= sc; fy *= sc; fz *= sc;
+                    if (active) nlim++;
                 }
                 us[g] = Vec4<R>{n, fx, fy, fz};
             }
             buf ^= 1;
         }
 
-        // roll the z window up before the chemistry so that plane z's state and
+        // roll the z window before the chemistry so that plane z's state and
         // closure are dead while it runs: 2 A_z(plane z) for the next plane
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             Az2[g] = az2(cur[g], Pc[g], c);
-            cur[g] = nxt[g];
+            if (!FUSE) {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) Pc[g][q] = Pn[g][q];
+                for (int q = 0; q < 6; ++q) Pc[g][q] = Pn[g][q];
+            }
         }
+        // the slots of plane z are free: refill them with plane z + U (clamped
+        // to the chunk's last plane, which is then loaded twice from L2); the
+        // loads fly while the chemistry runs
+        load_cell<G>(a.N, a.F, V, (zwrap(min(z + U, z1)) * plane + col) * E, cur);
+        load_cell<G>(a.N, a.F, V, ((uint32_t)min(z + U, z1 - 1) * plane + hsrc) * E, hal);
 
         bool deferred = false;
-        if (active) {
-            if (FUSE) {
-                double Nc[G], Fc[G][3], Sc[G];
+        if (FUSE && active) {
+            double Nc[G], Sc[G], Pf[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) Nc[g] = (double)us[g].n;
+            source_of<G>((int64_t)zc, a.src.mask, a.src.sorted_cell, a.src.S, a.src.n, Sc);
+            const ChemStats cs =
+                chem_cell_nxt<G, FAST>(a.gc, a.cp, Nc, Pf, xg, Tg, n0g, Sc, kChemBudgetFused, &deferred);
+            if (!deferred) {
+                if (DIAG) {
+                    tot.substeps += cs.substeps;
+                    tot.attempts += cs.attempts;
+                    tot.cap += cs.cap;
+                    tot.xclamp += cs.xclamp;
+                    maxsub = max(maxsub, cs.substeps);
+                }
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    Nc[g] = (double)us[g].n;
-                    Fc[g][0] = (double)us[g].fx;
-                    Fc[g][1] = (double)us[g].fy;
-                    Fc[g][2] = (double)us[g].fz;
+                    us[g].n = (R)Nc[g];
+                    us[g].fx = (R)((double)us[g].fx * Pf[g]);
+                    us[g].fy = (R)((double)us[g].fy * Pf[g]);
+                    us[g].fz = (R)((double)us[g].fz * Pf[g]);
                 }
-                source_of<G>((int64_t)zc, a.src.mask, a.src.sorted_cell, a.src.S, a.src.n, Sc);
-                const ChemStats cs =
-                    chem_cell<G, FAST>(a.gc, a.cp, Nc, Fc, xg, Tg, n0g, Sc, kChemBudget, &deferred);
-                if (!deferred) {
-                    if (DIAG) {
-                        tot.substeps += cs.substeps;
-                        tot.attempts += cs.attempts;
-                        tot.cap += cs.cap;
-                        tot.xclamp += cs.xclamp;
-                        maxsub = max(maxsub, cs.substeps);
-                    }
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        us[g].n = (R)Nc[g];
-                        us[g].fx = (R)Fc[g][0];
-                        us[g].fy = (R)Fc[g][1];
-                        us[g].fz = (R)Fc[g][2];
-                    }
-                    st(a.x, zc * 8u, xg);
-                    st(a.T, zc * 8u, Tg);
-                }
-                // deferred: N*, F* go to the output below; x, T stay untouched
+                st(a.x, zc * 8u, xg);
+                st(a.T, zc * 8u, Tg);
             }
+            // deferred: N*, F* go to the output below; x, T stay untouched
+        }
+        if (active) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 st(a.No + (int64_t)g * V, zc * E, us[g].n);
@@ -279,13 +386,18 @@ __global__ __launch_bounds__(256) void k_tiled(TileArgs<R> a) {
 
         if (FUSE) defer_push(a.wl, deferred, zc);
 
-        // the prefetched plane z+2 becomes plane z+1 of the next iteration
+        // plane z + 2 becomes the next step's upper neighbour
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (active) nxt[g] = nn[g];
-            m1_pressure(nxt[g].n, nxt[g].fx, nxt[g].fy, nxt[g].fz, c, Pn[g]);
-            if (hrole >= 0 && z + 1 < z1) hal[g] = hnext[g];
+            if (z + 2 == nz && zhi_ghost) nn[g] = ghost4(bd, 5, g, c, nxt[g]);  // nxt = plane nz-1
+            m1_pressure(nn[g].n, nn[g].fx, nn[g].fy, nn[g].fz, c, Pn[g]);
+            Bz2[g] = bz2(nn[g], Pn[g], c);
         }
+    };
+    for (int zb = z0; zb < z1; zb += U) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (zb + j < z1) plane_step(zb + j, W[j], W[(j + 1) % U], W[(j + 2) % U], H[j]);
     }
     if (DIAG) {
         wave_count(a.cnt, CNT_LIMITER, nlim);
@@ -304,13 +416,13 @@ template <int G, typename S>
 inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, double *T,
                              const double *n0, const Grid &gr, const SrcTable &src,
                              const GroupConsts &gc, const ChemParams &cp, double lam,
-                             unsigned long long *cnt, int LZ, WorkList wl) {
+                             unsigned long long *cnt, int LZ, WorkList wl, int TY, const Bounds<S> &bnd) {
     TileArgs<S> a;
     a.N = iN; a.F = iF; a.No = oN; a.Fo = oF;
     a.x = x; a.T = T; a.n0 = n0;
     a.gr = gr;
     a.ntx = (gr.nx + kTX - 1) / kTX;
-    a.nty = (gr.ny + kTY - 1) / kTY;
+    a.nty = (gr.ny + TY - 1) / TY;
     a.LZ = LZ;
     a.ntz = (gr.nz + LZ - 1) / LZ;
     a.c = (S)cp.c;
@@ -320,13 +432,14 @@ inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, 
     a.cp = cp;
     a.cnt = cnt;
     a.wl = wl;
+    a.bnd = bnd;
     return a;
 }
 
 // Number of z planes per block: enough blocks to fill 256 CUs several times.
-inline int pick_lz(const Grid &gr) {
-    const int64_t cols = (int64_t)((gr.nx + kTX - 1) / kTX) * ((gr.ny + kTY - 1) / kTY);
-    int lz = 32;
+inline int pick_lz(const Grid &gr, int TY) {
+    const int64_t cols = (int64_t)((gr.nx + kTX - 1) / kTX) * ((gr.ny + TY - 1) / TY);
+    int lz = EMMA_LZ_MAX;
     while (lz > 4 && cols * ((gr.nz + lz - 1) / lz) < 2048) lz >>= 1;
     return lz;
 }
@@ -335,18 +448,28 @@ inline int pick_lz(const Grid &gr) {
 // double fields: V * 8 bytes must stay below 4 GiB.
 inline bool tiled_supported(const Grid &gr) { return (uint64_t)gr.V * 8 < ((uint64_t)1 << 32); }
 
-// Transport only (split path): one group per block, grid.y = group, which
-// keeps one group's rolling window in registers instead of all G.
+// Transport only (split path): one launch per group, which keeps one
+// group's rolling window in registers instead of all G.
 template <int G, typename S, bool DIAG>
 inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
-                                  const ChemParams &cp, double lam, unsigned long long *cnt) {
-    const int LZ = pick_lz(gr);
+                                  const ChemParams &cp, double lam, unsigned long long *cnt,
+                                  const Bounds<S> &bnd) {
+    // double tiles need twice the LDS: at most 8 rows (136 KB)
+    constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
+    const int LZ = pick_lz(gr, TY);
     for (int g = 0; g < G; ++g) {
+        Bounds<S> bg = bnd;  // this launch's group is group 0 of the kernel
+        for (int f = 0; f < 6; ++f) bg.phi[f][0] = bnd.phi[f][g];
         TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
                                         oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
-                                        GroupConsts{}, cp, lam, cnt, LZ, WorkList{});
+                                        GroupConsts{}, cp, lam, cnt, LZ, WorkList{}, TY, bg);
         const int nb = a.ntx * a.nty * a.ntz;
-        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+        if (gr.nx % kTX == 0 && gr.ny % TY == 0)
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, true>), dim3(nb),
+                               dim3(kTX * TY), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, false>), dim3(nb),
+                               dim3(kTX * TY), 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -354,14 +477,23 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
 template <int G, typename S, bool DIAG>
 inline int launch_fused(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, double *x, double *T,
                         const double *n0, const Grid &gr, const SrcTable &src, const GroupConsts &gc,
-                        const ChemParams &cp, double lam, unsigned long long *cnt, WorkList wl) {
-    const int LZ = pick_lz(gr);
-    TileArgs<S> a = tile_args<G, S>(iN, iF, oN, oF, x, T, n0, gr, src, gc, cp, lam, cnt, LZ, wl);
+                        const ChemParams &cp, double lam, unsigned long long *cnt, WorkList wl,
+                        const Bounds<S> &bnd) {
+    constexpr int TY = (sizeof(S) == 8 && EMMA_TY_FUSED > 8) ? 8 : EMMA_TY_FUSED;
+    const int LZ = pick_lz(gr, TY);
+    TileArgs<S> a = tile_args<G, S>(iN, iF, oN, oF, x, T, n0, gr, src, gc, cp, lam, cnt, LZ, wl, TY, bnd);
     const int nb = a.ntx * a.nty * a.ntz;
-    if (cp.otsa && !cp.isothermal)
-        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, true>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+    const bool full = gr.nx % kTX == 0 && gr.ny % TY == 0;
+    const bool fast = cp.otsa && !cp.isothermal;
+    if (fast && full)
+        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, true, TY, EMMA_PD_FUSED, true>), dim3(nb), dim3(kTX * TY), 0,
+                           st, a);
+    else if (fast)
+        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, true, TY, EMMA_PD_FUSED, false>), dim3(nb), dim3(kTX * TY), 0,
+                           st, a);
     else
-        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, false>), dim3(nb), dim3(kTX * kTY), 0, st, a);
+        hipLaunchKernelGGL((k_tiled<G, S, DIAG, true, false, TY, EMMA_PD_FUSED, false>), dim3(nb), dim3(kTX * TY),
+                           0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

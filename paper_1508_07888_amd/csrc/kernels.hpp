@@ -14,6 +14,7 @@
 #pragma once
 
 #include "physics.hpp"
+#include "../../include/emma_rt.h"
 
 namespace emma {
 
@@ -169,6 +170,71 @@ struct SrcTable {
     int n;
 };
 
+// --------------------------------------------------------------- boundaries
+// Global boundaries (the gather step of Sec. 4 and the planar source of the
+// Sec. 6 photo-evaporation test), faces x-, x+, y-, y+, z-, z+.  Across a
+// non-periodic face the outside neighbour of a cell is a ghost made from the
+// cell itself: transmissive = the cell; reflective = the cell with its normal
+// flux component reversed; inflow = a beam entering along the face normal,
+// F = phi_g n_in, N = phi_g / c, independent of the cell.
+enum BcKind { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
+
+template <typename R>
+struct Bounds {
+    int kind[6];
+    R phi[6][EMMA_RT_MAX_GROUPS];  // inflow faces: photons cm^-2 s^-1 of each group
+};
+
+// Turn the state (n, f[3]) of the boundary cell into its ghost across face.
+template <typename R>
+__host__ __device__ __forceinline__ void ghost(const Bounds<R> &b, int face, int g, R c, R &n, R f[3]) {
+    const int d = face >> 1;
+    const int k = b.kind[face];
+    if (k == BC_REFLECTIVE) {
+        f[d] = -f[d];
+    } else if (k == BC_INFLOW) {
+        const R phi = b.phi[face][g];
+        n = phi / c;
+        f[0] = R(0); f[1] = R(0); f[2] = R(0);
+        f[d] = (face & 1) ? -phi : phi;  // pointing into the domain
+    }
+}
+
+// Neighbour cells of cell (x, y, z) across both faces of each axis: flat
+// index (the cell itself across a non-periodic face) and the face whose
+// ghost applies there (-1: an ordinary neighbour).
+struct Nbrs {
+    int64_t idx[3][2];
+    int face[3][2];
+};
+
+template <typename R>
+__host__ __device__ inline Nbrs neighbours(const Grid &gr, const Bounds<R> &b, int64_t i, int x, int y, int z) {
+    Nbrs nb;
+    const int c3[3] = {x, y, z};
+    const int n3[3] = {gr.nx, gr.ny, gr.nz};
+    const int64_t st[3] = {1, (int64_t)gr.nx, (int64_t)gr.nx * gr.ny};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int face = 2 * d + s;
+            int q = c3[d] + (s ? 1 : -1);
+            nb.face[d][s] = -1;
+            if (q < 0 || q >= n3[d]) {
+                if (b.kind[face] == BC_PERIODIC) {
+                    q = s ? 0 : n3[d] - 1;
+                } else {
+                    q = c3[d];
+                    nb.face[d][s] = face;
+                }
+            }
+            nb.idx[d][s] = i + (int64_t)(q - c3[d]) * st[d];
+        }
+    }
+    return nb;
+}
+
 // ---------------------------------------------------------------- transport
 // Reference transport: one thread per cell, all groups.  The update of cell i
 // is U* = U + (dt/dx) sum_d [flux(i-1/2) - flux(i+1/2)] with the flux of
@@ -184,12 +250,36 @@ __device__ inline void glf(R NL, const R FL[3], const R PL[6], R NR, const R FR[
         out[1 + k] = R(0.5) * c * c * (PL[col[k][d]] + PR[col[k][d]]) - R(0.5) * c * (FR[k] - FL[k]);
 }
 
+// HLL flux across a face normal to axis d with the speeds of m1_speeds:
+//   (a+ Ft(L) - a- Ft(R) + a+ a- (U_R - U_L)) / (a+ - a-),
+// a- = min(0, speeds of both sides), a+ = max(0, speeds of both sides).
+template <typename R>
+__device__ inline void hll(R NL, const R FL[3], const R PL[6], R NR, const R FR[3], const R PR[6], int d, R c,
+                           R out[4]) {
+    const int col[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    // speeds in double: the radicand is O((1 - |f|)^2) from O(1) terms, which
+    // would leave sqrt(eps) errors in single precision
+    double lmL, lpL, lmR, lpR;
+    m1_speeds<double>(NL, FL[d], c, lmL, lpL);
+    m1_speeds<double>(NR, FR[d], c, lmR, lpR);
+    double amd = lmL < lmR ? lmL : lmR;
+    double apd = lpL > lpR ? lpL : lpR;
+    const R am = (R)(amd < 0.0 ? amd : 0.0);
+    const R ap = (R)(apd > 0.0 ? apd : 0.0);
+    const R inv = FastMath<R>::rcp(ap - am);
+    const R cc = c * c, pm = ap * am;
+    out[0] = (ap * FL[d] - am * FR[d] + pm * (NR - NL)) * inv;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        out[1 + k] = (ap * cc * PL[col[k][d]] - am * cc * PR[col[k][d]] + pm * (FR[k] - FL[k])) * inv;
+}
+
 // NOLIMIT = true skips the floor and limiter (the adjoint needs the values
-// before them).
-template <int G, typename R, bool DIAG, bool NOLIMIT = false>
+// before them).  HLLF selects the HLL flux instead of eq. (e:glf).
+template <int G, typename R, bool DIAG, bool NOLIMIT = false, bool HLLF = false>
 __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, const R *__restrict__ F,
                                                    R *__restrict__ Ns, R *__restrict__ Fs, Grid gr,
-                                                   R c, R lam, unsigned long long *cnt) {
+                                                   R c, R lam, unsigned long long *cnt, Bounds<R> bnd) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < gr.V;
     int64_t nlim = 0, nneg = 0;
@@ -198,21 +288,7 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
         const int y = (int)((i / gr.nx) % gr.ny);
         const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
         const int64_t V = gr.V;
-        int64_t nb[3][2];
-        {
-            const int xm = x == 0 ? gr.nx - 1 : x - 1, xp = x == gr.nx - 1 ? 0 : x + 1;
-            const int ym = y == 0 ? gr.ny - 1 : y - 1, yp = y == gr.ny - 1 ? 0 : y + 1;
-            const int zm = z == 0 ? gr.nz - 1 : z - 1, zp = z == gr.nz - 1 ? 0 : z + 1;
-            const int64_t row = (int64_t)gr.nx;
-            const int64_t pl = (int64_t)gr.nx * gr.ny;
-            const int64_t base = i - x;
-            nb[0][0] = base + xm;
-            nb[0][1] = base + xp;
-            nb[1][0] = i + (int64_t)(ym - y) * row;
-            nb[1][1] = i + (int64_t)(yp - y) * row;
-            nb[2][0] = i + (int64_t)(zm - z) * pl;
-            nb[2][1] = i + (int64_t)(zp - z) * pl;
-        }
+        const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const R *Ng = N + (int64_t)g * V;
@@ -224,16 +300,23 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
             R acc[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int64_t im = nb[d][0], ip = nb[d][1];
-                const R Nm = Ng[im], Np = Ng[ip];
-                const R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
-                const R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
+                const int64_t im = nb.idx[d][0], ip = nb.idx[d][1];
+                R Nm = Ng[im], Np = Ng[ip];
+                R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
+                R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
+                if (nb.face[d][0] >= 0) ghost(bnd, nb.face[d][0], g, c, Nm, Fm);
+                if (nb.face[d][1] >= 0) ghost(bnd, nb.face[d][1], g, c, Np, Fp);
                 R Pm[6], Pp[6];
                 m1_pressure(Nm, Fm[0], Fm[1], Fm[2], c, Pm);
                 m1_pressure(Np, Fp[0], Fp[1], Fp[2], c, Pp);
                 R lo[4], hi[4];
-                glf(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
-                glf(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+                if (HLLF) {
+                    hll(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
+                    hll(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+                } else {
+                    glf(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
+                    glf(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+                }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) acc[k] += lo[k] - hi[k];
             }
@@ -267,7 +350,14 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
 // near the sources need tens to hundreds, and in place they would hold their
 // whole wave for that long.  They are finished by a second, persistent pass
 // over the compacted list (same code, same inputs, same results).
-constexpr int kChemBudget = 4;
+#ifndef EMMA_CHEM_BUDGET
+#define EMMA_CHEM_BUDGET 4
+#endif
+#ifndef EMMA_CHEM_BUDGET_FUSED
+#define EMMA_CHEM_BUDGET_FUSED 2
+#endif
+constexpr int kChemBudget = EMMA_CHEM_BUDGET;
+constexpr int kChemBudgetFused = EMMA_CHEM_BUDGET_FUSED;
 
 struct WorkList {
     uint32_t *count;  // [1], reset before every first pass

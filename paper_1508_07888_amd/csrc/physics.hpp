@@ -54,28 +54,69 @@ template <> struct FastMath<double> {
     __device__ static inline double div(double a, double b) { return a / b; }
 };
 
-// With n = F/|F| and f^2 = |F|^2 / (c N)^2, P = a I + (b/|F|^2) F F^T where
-// a = (1 - chi)/2 N and b = (3 chi - 1)/2 N; chi depends on f^2 only, so no
-// square root of |F|^2 and no normalisation of F is needed.
+// Eddington tensor closure (R2-R4 of the readings): P = D N with
+// D = (1 - chi)/2 I + (3 chi - 1)/2 n n^T, f = |F|/(c N) clipped at 1.
+// Written with the reduced flux g = F/(c N) (|g| = f, an O(1) vector), so no
+// square of a tiny |F| appears: for the faint fields ahead of a front, |F|^2
+// underflows to a denormal long before g does.  With q = |g|^2 and
+// s = sqrt(4 - 3q):
+//   a = (1 - chi)/2 N = (1 + s - 2q)/(5 + 2s) N,
+//   (3 chi - 1)/2 n n^T = q h(q) g g^T / q = h(q) g g^T,  h = (6 + 3/(2 + s))/(5 + 2s),
+// free of cancellation at small q; at the clip (q >= 1) chi = 1 and
+// P = N g g^T / q.
 template <typename R>
 __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) {
     using M = FastMath<R>;
-    const R F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-    R a = N * R(1.0 / 3.0), bq = R(0);  // chi = 1/3 when N <= 0 or F = 0
-    if (N > R(0) && F2 > R(0)) {
+    R a = N * R(1.0 / 3.0), k = R(0);  // chi = 1/3 when N <= 0
+    R gx = R(0), gy = R(0), gz = R(0);
+    if (N > R(0)) {
         const R icn = M::rcp(c * N);
-        R f2 = (F2 * icn) * icn;
-        f2 = f2 < R(1) ? f2 : R(1);
-        const R chi = (R(3) + R(4) * f2) * M::rcp(R(5) + R(2) * M::sqrt(R(4) - R(3) * f2));
-        a = R(0.5) * (R(1) - chi) * N;
-        bq = R(0.5) * (R(3) * chi - R(1)) * N * M::rcp(F2);
+        gx = Fx * icn;
+        gy = Fy * icn;
+        gz = Fz * icn;
+        const R q = gx * gx + gy * gy + gz * gz;
+        if (q < R(1)) {
+            const R s = M::sqrt(R(4) - R(3) * q);
+            const R rd = M::rcp(R(5) + R(2) * s);
+            a = (R(1) + s - R(2) * q) * rd * N;
+            k = (R(6) + R(3) * M::rcp(R(2) + s)) * rd * N;
+        } else {  // f clipped at 1: chi = 1, P = N g g^T / q
+            a = R(0);
+            k = N * M::rcp(q);
+        }
     }
-    P[0] = a + bq * Fx * Fx;
-    P[1] = bq * Fx * Fy;
-    P[2] = bq * Fx * Fz;
-    P[3] = a + bq * Fy * Fy;
-    P[4] = bq * Fy * Fz;
-    P[5] = a + bq * Fz * Fz;
+    P[0] = a + k * gx * gx;
+    P[1] = k * gx * gy;
+    P[2] = k * gx * gz;
+    P[3] = a + k * gy * gy;
+    P[4] = k * gy * gz;
+    P[5] = a + k * gz * gz;
+}
+
+// Signal speeds along one axis for the HLL flux: the eigenvalues of the
+// one-dimensional M1 system (N, F_d) -> (F_d, c^2 chi(f) N) at the normal
+// reduced flux f = F_d/(c N) in [-1, 1] (0 when N <= 0):
+//   lambda = c (chi' -+ sqrt(chi'^2 + 4 (chi - f chi')))/2.
+// The radicand is O((1 - |f|)^2) near |f| = 1 and is kept >= 0.
+template <typename R>
+__device__ __forceinline__ void m1_speeds(R N, R Fd, R c, R &lmin, R &lmax) {
+    using M = FastMath<R>;
+    R f = R(0);
+    if (N > R(0)) {
+        f = M::div(Fd, c * N);
+        f = f < R(-1) ? R(-1) : (f > R(1) ? R(1) : f);
+    }
+    const R s = M::sqrt(R(4) - R(3) * f * f);
+    const R den = R(5) + R(2) * s;
+    const R iden = M::rcp(den);
+    const R num = R(3) + R(4) * f * f;
+    const R chi = num * iden;
+    const R dchi = (R(8) * f * den + R(6) * f * num * M::rcp(s)) * iden * iden;
+    R rad = dchi * dchi + R(4) * (chi - f * dchi);
+    rad = rad > R(0) ? rad : R(0);
+    const R root = M::sqrt(rad);
+    lmin = R(0.5) * c * (dchi - root);
+    lmax = R(0.5) * c * (dchi + root);
 }
 
 // ------------------------------------------------------------------- rates
@@ -273,6 +314,38 @@ __host__ __device__ __forceinline__ bool substep(const GroupConsts &gc, const Ch
     rem = rem - dtau;
     st.substeps++;
     return true;
+}
+
+// The subcycle without F: F only ever gets multiplied by the substeps'
+// factors, so the caller applies their product Pf[g] to F afterwards
+// (F_out = F_in Pf).  Same budget semantics as chem_cell.
+template <int G, bool FAST = false>
+__host__ __device__ __forceinline__ ChemStats chem_cell_nxt(const GroupConsts &gc, const ChemParams &p,
+                                                            double (&N)[G], double (&Pf)[G], double &x,
+                                                            double &T, double n0, const double (&S)[G],
+                                                            int budget = 0x7fffffff, bool *deferred = nullptr) {
+    ChemStats st{0, 0, 0, 0};
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    const double eunit = 1.5 * n0 * kKB;  // e = eunit (1 + x) T
+    double e = eunit * (1.0 + x) * T;
+    double rem = p.dt;
+#pragma unroll
+    for (int g = 0; g < G; ++g) Pf[g] = 1.0;
+    while (rem > 0.0) {
+        if (st.substeps >= budget) {
+            *deferred = true;
+            return st;
+        }
+        const bool last = st.substeps >= p.max_substeps;
+        double inv[G];
+        if (!substep<G, FAST>(gc, p, last, n0, eunit, T, S, N, x, e, rem, inv, st, nullptr)) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g) Pf[g] *= inv[g];
+        if (last) { st.cap = 1; break; }
+        if (iso) break;
+    }
+    if (!iso) T = e / (eunit * (1.0 + x));
+    return st;
 }
 
 // The sub-cycled update of one cell over dt.  N[g], F[g][3] hold the

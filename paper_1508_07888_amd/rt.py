@@ -32,7 +32,8 @@ class EmmaRT:
 
     def __init__(self, shape, n_groups, dx, c_red, precision="mixed", groups=None, T_bb=1e5,
                  edges_eV=None, otsa=True, isothermal=False, max_substeps=100000,
-                 adjoint_max_steps=0, path="fused", device="cuda:0"):
+                 adjoint_max_steps=0, path="fused", device="cuda:0", bc=None, inflow=None,
+                 flux="glf"):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)
         self.G = int(n_groups)
@@ -60,6 +61,18 @@ class EmmaRT:
             raise ValueError(f"path must be one of {sorted(_lib.PATHS)}")
         cfg.path = _lib.PATHS[path]
         self.path = path
+        # faces x-, x+, y-, y+, z-, z+: names of _lib.BCS; inflow in photons cm^-2 s^-1
+        bc = ["periodic"] * 6 if bc is None else list(bc)
+        inflow = [0.0] * 6 if inflow is None else [float(v) for v in inflow]
+        if len(bc) != 6 or len(inflow) != 6:
+            raise ValueError("bc and inflow need one entry per face (x-, x+, y-, y+, z-, z+)")
+        for f in range(6):
+            cfg.bc[f] = _lib.BCS[bc[f]] if isinstance(bc[f], str) else int(bc[f])
+            cfg.inflow[f] = inflow[f]
+        if flux not in _lib.FLUXES:
+            raise ValueError(f"flux must be one of {sorted(_lib.FLUXES)}")
+        cfg.flux = _lib.FLUXES[flux]
+        self.bc, self.inflow, self.flux = bc, inflow, flux
         for g in range(self.G):
             cfg.sigma_N[g] = self.groups["sigma_N"][g]
             cfg.sigma_E[g] = self.groups["sigma_E"][g]

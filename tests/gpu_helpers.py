@@ -15,12 +15,14 @@ def to_dev(a, dtype=torch.float64):
 
 
 def run_gpu(N, F, x, T, n0, cells, rates, *, dx, c_red, dt, n_steps, groups, precision="fp64",
-            otsa=1, isothermal=0, max_substeps=100000, diag=True, rt=None, path="fused"):
+            otsa=1, isothermal=0, max_substeps=100000, diag=True, rt=None, path="fused", bc=None,
+            inflow=None, flux="glf"):
     G = N.shape[0]
     own = rt is None
     if own:
         rt = EmmaRT(n0.shape, G, dx, c_red, precision=precision, groups=groups, otsa=otsa,
-                    isothermal=isothermal, max_substeps=max_substeps, path=path, device=DEV)
+                    isothermal=isothermal, max_substeps=max_substeps, path=path, device=DEV,
+                    bc=bc, inflow=inflow, flux=flux)
     fdt = rt.dtype
     gN, gF = to_dev(N, fdt), to_dev(F, fdt)
     gx, gT, gn = to_dev(x), to_dev(T), to_dev(n0)

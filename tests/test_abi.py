@@ -4,6 +4,7 @@ GPU, and its own group-constant quadrature agrees with the oracle's."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -29,11 +30,27 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, n), n
 
 
-def test_struct_layouts_match_header():
-    # offsets the header implies (int32 x4, double x2, int32 x6, double[4] x4)
-    assert ctypes.sizeof(_lib.emma_rt_config) == 16 + 16 + 24 + 4 * 32
-    assert _lib.emma_rt_config.sigma_N.offset == 56
-    assert ctypes.sizeof(_lib.emma_rt_diag) == 32 + 8 + 16 + 8 + 40
+def _c_layout(struct, fields, tmp_path):
+    """sizeof and offsetof of a header struct, from a program compiled against it."""
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{ROOT}/include/emma_rt.h"',
+             "int main(void) {", f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("name", ["emma_rt_config", "emma_rt_diag", "emma_rt_kernel_time"])
+def test_struct_layouts_match_header(name, tmp_path):
+    cls = getattr(_lib, name)
+    fields = [f[0] for f in cls._fields_]
+    got = _c_layout(name, fields, tmp_path)
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, f).offset for f in fields]
 
 
 def _cfg(**kw):
@@ -55,6 +72,11 @@ def _cfg(**kw):
     (dict(nx=0), "grid"), (dict(n_groups=5), "n_groups"), (dict(n_groups=0), "n_groups"),
     (dict(dx=0.0), "dx"), (dict(c_red=4e10), "c_red"), (dict(precision=7), "precision"),
     (dict(max_substeps=0), "max_substeps"), (dict(adjoint_max_steps=-1), "adjoint"),
+    (dict(bc=(ctypes.c_int32 * 6)(1, 0, 0, 0, 0, 0)), "periodic or neither"),
+    (dict(bc=(ctypes.c_int32 * 6)(0, 0, 4, 4, 0, 0)), "bc values"),
+    (dict(inflow=(ctypes.c_double * 6)(0, 0, 0, -1.0, 0, 0)), "inflow"),
+    (dict(flux=2), "flux"), (dict(flux=1), "reference path"),
+    (dict(flux=1, path=2, adjoint_max_steps=2), "GLF flux only"),
 ])
 def test_init_rejects_bad_config(kw, msg):
     L = _lib.load()

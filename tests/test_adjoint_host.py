@@ -184,7 +184,8 @@ int main() {
     double N, fx, fy, fz, c;
     while (scanf("%lf %lf %lf %lf %lf", &N, &fx, &fy, &fz, &c) == 5) {
         emma::ClosureJac j = emma::closure_jac(N, fx, fy, fz, c);
-        printf("%.17g %.17g %.17g %.17g %.17g\n", j.aN, j.ga, j.bq, j.bqN, j.gb);
+        printf("%.17g %.17g %.17g %.17g %.17g %.17g %.17g %.17g\n", j.aN, j.GA, j.K, j.KN, j.GB,
+               j.g[0], j.g[1], j.g[2]);
     }
     return 0;
 }
@@ -209,13 +210,20 @@ def test_closure_jacobian_matches_oracle_pressure_differences():
         dvec /= np.linalg.norm(dvec)
         N = 10 ** rng.uniform(-3, 1)
         cases.append((N, *(f * c * N * dvec)))
-    inp = "\n".join(" ".join(repr(float(v)) for v in (*cs, c)) for cs in cases)
+    # faint fields: |F|^2 and (c N)^-4 far outside the double range
+    faint = [(1e-250, 0.3 * c * 1e-250, 0.0, 0.0), (1e-300, 0.0, 1.0 * c * 1e-300, 0.0)]
+    inp = "\n".join(" ".join(repr(float(v)) for v in (*cs, c)) for cs in cases + faint)
     out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for line in out[len(cases):len(cases) + len(faint)]:
+        vals = np.array([float(v) for v in line.split()])
+        assert np.all(np.isfinite(vals)) and np.max(np.abs(vals)) < 10
     for cs, line in zip(cases, out):
-        aN, ga, bq, bqN, gb = map(float, line.split())
+        aN, GA, K, KN, GB, *gv = map(float, line.split())
+        g = np.array(gv)
         N, F = cs[0], np.array(cs[1:])
-        # analytic dP/dN and dP/dF_k from the Jacobian pieces
-        dPdN = aN * np.eye(3) + bqN * np.outer(F, F)
+        # analytic dP/dN and dP/dF_k from the Jacobian pieces (g = F/(c N))
+        assert np.allclose(g, F / (c * N), rtol=1e-15, atol=0)
+        dPdN = aN * np.eye(3) + KN * np.outer(g, g)
         h = 1e-6
         Fn = np.linalg.norm(F)
         if Fn >= c * N * (1 - 1e-3):
@@ -230,7 +238,7 @@ def test_closure_jacobian_matches_oracle_pressure_differences():
         for k in range(3):
             e = np.zeros(3)
             e[k] = 1.0
-            dPdF = ga * F[k] * np.eye(3) + gb * F[k] * np.outer(F, F) + bq * (np.outer(e, F) + np.outer(F, e))
+            dPdF = (GA * g[k] * np.eye(3) + GB * g[k] * np.outer(g, g) + K * (np.outer(e, g) + np.outer(g, e))) / c
             step = h * Fn
             num_F = (oracle.pressure(N, F + step * e, c) - oracle.pressure(N, F - step * e, c)) / (2 * step)
             assert np.allclose(dPdF, num_F, rtol=1e-5, atol=1e-6 * N / Fn)

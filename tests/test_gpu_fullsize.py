@@ -1,0 +1,221 @@
+"""The full-size workloads in the benchmark's launch configuration (fused
+path, one emma_rt_step call, no diagnostics), checked against the oracle on
+sampled cells.
+
+After k steps a cell depends only on the cells within k face-neighbour hops
+(radius-1 stencil, sources injected in their own cell), so the oracle run for
+k steps on the (2r+1)^3 block around a cell (r > k, extracted with the grid's
+periodic wrap, sources inside the block kept in list order) gives that cell's
+exact value; the block's own periodic wrap corrupts only cells within k of
+its faces.  Where the whole run is longer than the oracle can follow block by
+block, cells farther than k hops from every source see no radiation at all,
+and the oracle on the single cell gives them exactly; global properties that
+hold at any size (finite, x in [0, 1], N >= 0, |F| <= c N, photons in the box
+never more than emitted) cover the rest.
+
+Tolerances as in the parity tests: FP64 1e-12 normwise; mixed 1e-4 on N and
+F, 1e-6 absolute on x_HII, 1e-3 on T, normwise over the sampled cells.
+"""
+import numpy as np
+import pytest
+import torch
+
+import emma_inputs as E
+import oracle
+from gpu_helpers import DEV, groups_for, to_dev
+from sampling import block as _block, coords as _coords, hops_to_sources as _hops_to_sources
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _gpu_run(w, precision, steps, groups=None):
+    from paper_1508_07888_amd import EmmaRT
+    G = w["G"]
+    if groups is None:  # exactly the benchmark's context
+        rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"],
+                    edges_eV=w["edges"], path="fused", device=DEV)
+    else:
+        rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, groups=groups,
+                    path="fused", device=DEV)
+    fdt = rt.dtype
+    N, F = to_dev(w["N"], fdt), to_dev(w["F"], fdt)
+    x, T, n0 = to_dev(w["x"]), to_dev(w["T"]), to_dev(w["n0"])
+    cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
+    rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=steps)
+    torch.cuda.synchronize()
+    rt.close()
+    return N, F, x, T
+
+
+def _sample_compare(w, gpu, samples, steps, precision, label):
+    """Oracle on the block around each sampled cell vs the GPU at that cell."""
+    N, F, x, T = gpu
+    G = w["G"]
+    g = groups_for(G)
+    r = steps + 1
+    o_N, o_F, o_x, o_T, g_N, g_F, g_x, g_T = ([] for _ in range(8))
+    for cell in samples:
+        cz, cy, cx = (int(v) for v in _coords(np.int64(cell), w["shape"]))
+        bN, bF, bx, bT, bn0, bc, br = _block(w, (cz, cy, cx), r)
+        oN, oF, ox, oT, _ = oracle.run(bN, bF, bx, bT, bn0, bc, br, dx=w["dx"], c_red=w["c_red"],
+                                       dt=w["dt"], n_steps=steps, groups=g)
+        o_N.append(oN[:, r, r, r]); o_F.append(oF[:, :, r, r, r])
+        o_x.append(ox[r, r, r]); o_T.append(oT[r, r, r])
+        g_N.append(N[:, cz, cy, cx].double().cpu().numpy())
+        g_F.append(F[:, :, cz, cy, cx].double().cpu().numpy())
+        g_x.append(float(x[cz, cy, cx])); g_T.append(float(T[cz, cy, cx]))
+    o_N, o_F, g_N, g_F = (np.array(a) for a in (o_N, o_F, g_N, g_F))
+    o_x, o_T, g_x, g_T = (np.array(a) for a in (o_x, o_T, g_x, g_T))
+    assert np.abs(o_N).max() > 0  # the sample reaches lit cells
+    eN = [float(np.abs(g_N[:, k] - o_N[:, k]).max() / np.abs(o_N[:, k]).max()) for k in range(G)]
+    eF = [float(np.abs(g_F[:, k] - o_F[:, k]).max() / np.abs(o_F[:, k]).max()) for k in range(G)]
+    ex_abs = float(np.abs(g_x - o_x).max())
+    ex = ex_abs / float(np.abs(o_x).max())
+    eT = float(np.abs(g_T - o_T).max() / np.abs(o_T).max())
+    print(f"{label} {precision} ({len(samples)} cells, {steps} steps): N {eN} F {eF} "
+          f"x abs {ex_abs:.2e} T {eT:.2e}", flush=True)
+    if precision == "fp64":
+        assert max(eN) <= 1e-12 and max(eF) <= 1e-12 and ex <= 1e-12 and eT <= 1e-12
+    else:
+        assert max(eN) <= 1e-4 and max(eF) <= 1e-4 and ex_abs <= 1e-6 and eT <= 1e-3
+
+
+def _samples(w, n_each, seed):
+    rng = np.random.default_rng(seed)
+    shape = w["shape"]
+    V = int(np.prod(shape))
+    src = np.unique(w["src_cell"])[:n_each]
+    z, y, xx = _coords(src, shape)
+    off = ((z + 2) % shape[0] * shape[1] + (y + 1) % shape[1]) * shape[2] + (xx + 3) % shape[2]
+    return np.concatenate([src, off, rng.integers(0, V, n_each)]).astype(np.int64)
+
+
+def _properties(w, gpu, steps):
+    N, F, x, T = gpu
+    c = w["c_red"]
+    assert bool(torch.isfinite(N).all()) and bool(torch.isfinite(F).all())
+    assert bool(torch.isfinite(x).all()) and bool(torch.isfinite(T).all())
+    assert float(x.min()) >= 0.0 and float(x.max()) <= 1.0 and float(T.min()) > 0.0
+    assert float(N.min()) >= 0.0
+    Fm = torch.sqrt((F.double() ** 2).sum(dim=1))
+    assert bool((Fm <= c * N.double() * (1 + 1e-5) + 1e-300).all())
+    emitted = float(w["src_rate"].sum()) * steps * w["dt"]
+    photons = float(N.double().sum()) * w["dx"] ** 3
+    print(f"photons in box {photons:.6e} <= emitted {emitted:.6e}", flush=True)
+    assert 0.0 < photons <= emitted * (1 + 1e-5)
+
+
+def _far_cells_compare(w, gpu, steps, n_cells, seed):
+    """Cells farther than ``steps`` hops from every source: the oracle on the cell alone."""
+    N, F, x, T = gpu
+    rng = np.random.default_rng(seed)
+    V = int(np.prod(w["shape"]))
+    cand = rng.integers(0, V, 8 * n_cells)
+    far = cand[_hops_to_sources(cand, w) > steps + 1][:n_cells]
+    assert far.size >= n_cells // 2
+    z, y, xx = _coords(far, w["shape"])
+    g = groups_for(w["G"])
+    e_x = e_T = 0.0
+    for k in range(far.size):
+        sl = (slice(z[k], z[k] + 1), slice(y[k], y[k] + 1), slice(xx[k], xx[k] + 1))
+        oN, oF, ox, oT, _ = oracle.run(w["N"][(slice(None),) + sl], w["F"][(slice(None), slice(None)) + sl],
+                                       w["x"][sl], w["T"][sl], w["n0"][sl], np.zeros(0, np.int64),
+                                       np.zeros(0), dx=w["dx"], c_red=w["c_red"], dt=w["dt"],
+                                       n_steps=steps, groups=g)
+        assert float(N[:, z[k], y[k], xx[k]].abs().max()) == 0.0
+        e_x = max(e_x, abs(float(x[z[k], y[k], xx[k]]) - float(ox[0, 0, 0])))
+        e_T = max(e_T, abs(float(T[z[k], y[k], xx[k]]) / float(oT[0, 0, 0]) - 1))
+    print(f"{far.size} dark cells after {steps} steps: x abs {e_x:.2e} T rel {e_T:.2e}", flush=True)
+    assert e_x <= 1e-12 and e_T <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def w256():
+    return E.make_workload("throughput256")
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_throughput256_sampled_cells(w256, precision):
+    steps = 8
+    groups = None if precision == "mixed" else groups_for(w256["G"])
+    gpu = _gpu_run(w256, precision, steps, groups)
+    _sample_compare(w256, gpu, _samples(w256, 16, 1), steps, precision, "256^3")
+
+
+def test_throughput256_benchmark_run(w256):
+    # the timed run itself: 50 steps, mixed, one call
+    steps = w256["steps"]
+    gpu = _gpu_run(w256, "mixed", steps)
+    _properties(w256, gpu, steps)
+    _far_cells_compare(w256, gpu, steps, 128, 2)
+
+
+def test_large512_forward_and_adjoint():
+    from paper_1508_07888_amd import EmmaRT
+    w = E.make_workload("large512")
+    steps, K = w["steps"], w["K"]
+    gpu = _gpu_run(w, "mixed", steps)
+    _properties(w, gpu, steps)
+    _sample_compare(w, gpu, _samples(w, 3, 3), steps, "mixed", "512^3")
+    del gpu
+    torch.cuda.empty_cache()
+
+    # adjoint of K steps from the initial state (the tape holds all K states):
+    # loss = sum of x_HII at a few cells far apart; for each cell, the gradient
+    # contracted with a direction supported on the block around it must equal
+    # the oracle's dual-number tangent of that cell's x on the block
+    shape, G = w["shape"], w["G"]
+    rt = EmmaRT(shape, G, w["dx"], w["c_red"], precision="mixed", T_bb=w["T_bb"],
+                edges_eV=w["edges"], adjoint_max_steps=K, path="fused", device=DEV)
+    r = K + 1
+    src = np.unique(w["src_cell"])
+    chosen = []
+    for s in src:  # lit cells next to sources, blocks pairwise disjoint
+        c = np.array(_coords(np.int64(s), shape)) + np.array([1, 0, 1])
+        c %= np.array(shape)
+        if all(np.max(np.minimum(np.abs(c - o), np.array(shape) - np.abs(c - o))) > 2 * r + 1
+               for o in chosen):
+            chosen.append(c)
+        if len(chosen) == 4:
+            break
+    fdt = rt.dtype
+    N0, F0 = to_dev(w["N"], fdt), to_dev(w["F"], fdt)
+    x0, T0, n0 = to_dev(w["x"]), to_dev(w["T"]), to_dev(w["n0"])
+    cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
+    gN, gF = torch.zeros_like(N0), torch.zeros_like(F0)
+    gx, gT = torch.zeros_like(x0), torch.zeros_like(T0)
+    g_n0 = torch.zeros_like(n0)
+    g_rate = torch.zeros_like(rates)
+    for c in chosen:
+        gx[tuple(int(v) for v in c)] = 1.0
+    rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+    torch.cuda.synchronize()
+    rt.close()
+    g = groups_for(G)
+    rng = np.random.default_rng(7)
+    hN, hx, hT, hn0 = gN.cpu().numpy(), gx.cpu().numpy(), gT.cpu().numpy(), g_n0.cpu().numpy()
+    del gN, gF, gx, gT, g_n0, N0, F0, x0, T0, n0
+    torch.cuda.empty_cache()
+    assert len(chosen) == 4
+    for c in chosen:
+        cz, cy, cx = (int(v) for v in c)
+        bN, bF, bx, bT, bn0, bc, br = _block(w, (cz, cy, cx), r)
+        # N = F = 0 initially: perturb x, T, n0 (relative) and N (absolute scale)
+        dN = np.abs(rng.standard_normal(bN.shape)) * 1e-12
+        dF = np.zeros_like(bF)
+        dxh = bx * (1 - bx) * rng.standard_normal(bx.shape)
+        dT = bT * rng.standard_normal(bT.shape)
+        dn0 = bn0 * rng.standard_normal(bn0.shape)
+        _, (tN, tF, tx, tT), _ = oracle.run_tangent(bN, bF, bx, bT, bn0, bc, br, dN, dF, dxh, dT, dn0,
+                                                    np.zeros(br.shape), dx=w["dx"], c_red=w["c_red"],
+                                                    dt=w["dt"], n_steps=K, groups=g)
+        lhs = float(tx[r, r, r])
+        idx = [np.arange(v - r, v + r + 1) % n for v, n in zip((cz, cy, cx), shape)]
+        sel = np.ix_(*idx)
+        parts = [float((hN[(slice(None),) + sel].astype(np.float64) * dN).sum()),
+                 float((hx[sel] * dxh).sum()), float((hT[sel] * dT).sum()),
+                 float((hn0[sel] * dn0).sum())]
+        rhs = sum(parts)
+        scale = sum(abs(p) for p in parts)
+        print(f"cell {cz, cy, cx}: tangent {lhs:.10e} adjoint {rhs:.10e} parts {parts}", flush=True)
+        assert abs(lhs - rhs) <= 1e-3 * max(scale, abs(lhs))

@@ -210,3 +210,32 @@ def test_host_errors_on_device():
     d = rt.step(N, F, x, T, n0, cells, rates, dt=rt.max_dt(), diag=True)
     assert d["status"] == 0
     rt.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("precision,scale,check", [("mixed", 1e-24, True), ("mixed", 1e-27, False),
+                                                   ("mixed", 1e-31, False), ("fp64", 1e-161, True)])
+def test_tiny_fields_ahead_of_a_front_stay_finite(precision, scale, check, path):
+    # Radiation fields many orders of magnitude below the source's, as ahead
+    # of a diffusive front, with |F|^2 near or below the smallest normal
+    # number of the storage precision: the closure must neither overflow nor
+    # produce NaN (regression: bq = (3 chi - 1)/2 N / |F|^2 overflowed).
+    k = _random_case((20, 11, 12), 2, 31, n_src=0)
+    N, F = k["N"] * scale, k["F"] * scale
+    N[:, :5] = k["N"][:, :5]  # a lit slab next to the tiny region
+    F[:, :, :5] = k["F"][:, :, :5]
+    g = groups_for(2)
+    kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=3, groups=g)
+    ora = oracle.run(N, F, k["x"], k["T"], k["n0"], k["cells"], k["rates"], **kw)
+    gpu = run_gpu(N, F, k["x"], k["T"], k["n0"], k["cells"], k["rates"], precision=precision, path=path, **kw)
+    for a in gpu[:4]:
+        assert np.all(np.isfinite(a))
+    assert gpu[4]["nonfinite"] == 0
+    _compare(gpu, ora, precision, f"tiny {scale:g} {path}")
+    if check:
+        # the planes the lit slab has not reached, relative to their own scale
+        # (the storage precision still resolves |F|^2 there)
+        sl = (slice(None), slice(8, 17))
+        e = np.max(np.abs(gpu[0][sl] - ora[0][sl])) / np.max(np.abs(ora[0][sl]))
+        print(f"tiny region N: {e:.2e}", flush=True)
+        assert e <= (1e-12 if precision == "fp64" else 1e-4)
