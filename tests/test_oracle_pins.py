@@ -452,3 +452,46 @@ def test_stromgren32_early_front_bounded_by_photon_count():
     assert 0 < ionised <= emitted
     assert ionised + N.sum() * vol <= emitted * (1 + 1e-6)
     assert cnt["limiter"] == 0 and cnt["neg_clamp"] == 0
+
+
+# ------------------------------------------------ case A photon budget (f4)
+
+@pytest.mark.parametrize("otsa", [0, 1])
+def test_recombination_photon_budget(otsa):
+    # No source, isothermal ionised gas, one group (Sec. 2.2.4, eq. e:therm1g
+    # and the case-A recombination term): photons plus ionised atoms change
+    # only by the net case-B recombinations, sum (alpha_B x^2 - beta x (1-x)) n^2,
+    # whether the recombinations to the ground state re-emit an ionising photon
+    # (case A: alpha_A in the x update, (alpha_A - alpha_B) x^2 n^2 photons into
+    # group 1) or are left out (on the spot: alpha_B, no photons); exact up to
+    # O(dtau) terms of the per-substep sequence.
+    n, steps = 6, 4
+    c = 0.1 * C
+    dx = 1e20
+    dt = E.courant_dt(dx, c)
+    g = _groups(1)
+    T4 = 1e4
+    rng = np.random.default_rng(4)
+    x0 = rng.uniform(0.6, 0.95, (n, n, n))
+    N = np.zeros((1, n, n, n))
+    F = np.zeros((1, 3, n, n, n))
+    T = np.full((n, n, n), T4)
+    n0 = rng.uniform(0.5e-3, 2e-3, (n, n, n))
+    r = oracle.rates(T4)
+    aB, beta = r["alpha_B"], r["beta"]
+    vol = dx ** 3
+    x = x0
+    for _ in range(steps):
+        before = (N.sum() + (x * n0).sum()) * vol
+        rec0 = ((aB * x * x - beta * x * (1 - x)) * n0 ** 2).sum() * vol
+        N, F, x, T, cnt = oracle.run(N, F, x, T, n0, np.zeros(0, np.int64), np.zeros(0), dx=dx, c_red=c,
+                                     dt=dt, n_steps=1, groups=g, otsa=otsa, isothermal=1)
+        rec1 = ((aB * x * x - beta * x * (1 - x)) * n0 ** 2).sum() * vol
+        after = (N.sum() + (x * n0).sum()) * vol
+        change = after - before
+        expect = -0.5 * (rec0 + rec1) * dt
+        assert abs(change - expect) <= 1e-4 * abs(expect)
+        if otsa:
+            assert N.max() == 0.0
+        else:
+            assert N.min() > 0.0  # recombination photons were emitted
