@@ -53,6 +53,17 @@
  *       outside neighbour is a beam entering the domain along the face
  *       normal, F = Phi_g n_in and N = Phi_g / c (f = 1), where Phi_g is the
  *       face's photon flux density times the group's photon fraction.
+ *   R19 coarse radiative transport approximation (Sec. 5) with static
+ *       refinement: a refined coarse cell is split into r^3 children
+ *       (r = 2 or 4) that carry their own n0, x, T; each step the transport
+ *       runs on the coarse grid, the unrefined cells run their chemistry as
+ *       usual, every child runs the chemistry with its parent's N*, F*
+ *       injected (piecewise constant) and its own sources (child volume
+ *       (dx/r)^3), and the parent then holds the children's mean N, F, the
+ *       n0-weighted mean x and the (1+x) n0-weighted mean T (so the parent's
+ *       photons, ionised atoms and internal energy are the children's); the
+ *       means are pairwise sums over the children in index order
+ *       ((c0+c1)+(c2+c3))+... so that equal children give the parent exactly.
  *   R18 the HLL flux "on the way" in Sec. 2.2.3 takes as signal speeds along
  *       axis d the eigenvalues of the one-dimensional M1 system (N, F_d) at
  *       the normal reduced flux f_d = F_d/(c N) (clipped to [-1, 1], 0 when
@@ -470,6 +481,91 @@ void run_steps(const Params &p, int n_steps, R *N, R *F, R *x, R *T, const R *n0
     }
 }
 
+/* --------------------------------------- coarse transport, fine chemistry */
+/* Pairwise sum of v[0..n) (n a power of two) in index order (R19). */
+template <class R> R pair_sum(const R *v, int n) {
+    if (n == 1) return v[0];
+    return pair_sum(v, n / 2) + pair_sum(v + n / 2, n / 2);
+}
+
+/* n_steps steps of R19.  ref_cell[n_ref]: refined coarse cells (distinct);
+ * xf, Tf, nf: [n_ref][r^3] child fields, child index (cz r + cy) r + cx;
+ * Sc: coarse source densities (sources in unrefined cells), Sf: [n_ref r^3][G]
+ * child source densities. */
+template <class R>
+void run_crta(const Params &p, int n_steps, R *N, R *F, R *x, R *T, const R *n0, const std::vector<R> &Sc,
+              int n_ref, const int64_t *ref_cell, int ratio, R *xf, R *Tf, const R *nf, const std::vector<R> &Sf,
+              Counters &cnt) {
+    const int64_t V = (int64_t)p.nx * p.ny * p.nz;
+    const int G = p.G;
+    const int nc = ratio * ratio * ratio;
+    std::vector<char> refined((size_t)V, 0);
+    for (int j = 0; j < n_ref; ++j) refined[(size_t)ref_cell[j]] = 1;
+    std::vector<R> Ns((size_t)G * V), Fs((size_t)G * 3 * V);
+    std::vector<R> cN((size_t)nc), cF((size_t)nc), w((size_t)nc), tmp((size_t)nc);
+    for (int step = 0; step < n_steps; ++step) {
+        transport(p, N, F, Ns.data(), Fs.data(), cnt);
+        /* unrefined coarse cells: the ordinary chemistry */
+        for (int64_t i = 0; i < V; ++i) {
+            if (refined[(size_t)i]) continue;
+            R Nc[4], Fc[4][3], S[4];
+            for (int g = 0; g < G; ++g) {
+                Nc[g] = Ns[g * V + i];
+                for (int k = 0; k < 3; ++k) Fc[g][k] = Fs[((int64_t)g * 3 + k) * V + i];
+                S[g] = Sc[(size_t)i * G + g];
+            }
+            int att = 0, cap = 0, xcl = 0;
+            int ns = chem_cell(p, Nc, Fc, x[i], T[i], n0[i], S, &att, &cap, &xcl);
+            cnt.substeps += ns; cnt.attempts += att; cnt.cap_hits += cap; cnt.x_clamp += xcl;
+            if (ns > cnt.max_sub) cnt.max_sub = ns;
+            for (int g = 0; g < G; ++g) {
+                N[g * V + i] = Nc[g];
+                for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + i] = Fc[g][k];
+            }
+        }
+        /* refined cells: chemistry of every child with the parent's N*, F*, then restriction */
+        for (int j = 0; j < n_ref; ++j) {
+            const int64_t pi = ref_cell[j];
+            std::vector<R> chN((size_t)nc * G), chF((size_t)nc * G * 3);
+            for (int c = 0; c < nc; ++c) {
+                const size_t f = (size_t)j * nc + c;
+                R Nc[4], Fc[4][3], S[4];
+                for (int g = 0; g < G; ++g) {
+                    Nc[g] = Ns[g * V + pi];
+                    for (int k = 0; k < 3; ++k) Fc[g][k] = Fs[((int64_t)g * 3 + k) * V + pi];
+                    S[g] = Sf[f * G + g];
+                }
+                int att = 0, cap = 0, xcl = 0;
+                int ns = chem_cell(p, Nc, Fc, xf[f], Tf[f], nf[f], S, &att, &cap, &xcl);
+                cnt.substeps += ns; cnt.attempts += att; cnt.cap_hits += cap; cnt.x_clamp += xcl;
+                if (ns > cnt.max_sub) cnt.max_sub = ns;
+                for (int g = 0; g < G; ++g) {
+                    chN[(size_t)c * G + g] = Nc[g];
+                    for (int k = 0; k < 3; ++k) chF[((size_t)c * G + g) * 3 + k] = Fc[g][k];
+                }
+            }
+            const R inv = R(1.0 / nc);
+            for (int g = 0; g < G; ++g) {
+                for (int c = 0; c < nc; ++c) cN[c] = chN[(size_t)c * G + g];
+                N[g * V + pi] = pair_sum(cN.data(), nc) * inv;
+                for (int k = 0; k < 3; ++k) {
+                    for (int c = 0; c < nc; ++c) cF[c] = chF[((size_t)c * G + g) * 3 + k];
+                    F[((int64_t)g * 3 + k) * V + pi] = pair_sum(cF.data(), nc) * inv;
+                }
+            }
+            /* x: n0-weighted; T: (1+x) n0-weighted (internal energy e = 3/2 (1+x) n0 k_B T) */
+            const size_t f0 = (size_t)j * nc;
+            R nsum = pair_sum(nf + f0, nc);
+            for (int c = 0; c < nc; ++c) tmp[c] = xf[f0 + c] * (nf[f0 + c] / nsum);
+            x[pi] = pair_sum(tmp.data(), nc);
+            for (int c = 0; c < nc; ++c) w[c] = (1.0 + xf[f0 + c]) * nf[f0 + c];
+            R msum = pair_sum(w.data(), nc);
+            for (int c = 0; c < nc; ++c) tmp[c] = Tf[f0 + c] * (w[c] / msum);
+            T[pi] = pair_sum(tmp.data(), nc);
+        }
+    }
+}
+
 /* ------------------------------------------------------- photoionisation */
 /* Hydrogen photoionisation cross-section (exact hydrogenic form, Osterbrock &
  * Ferland), the paper cites a fit for it without printing one (R12):
@@ -609,6 +705,46 @@ int oracle_run_tangent(const int *ints, const double *dbls, const double *groups
         x[i] = dX[i].v; dx_[i] = dX[i].d;
         T[i] = dTT[i].v; dT[i] = dTT[i].d;
     }
+    export_counters(cnt, counters);
+    return 0;
+}
+
+/* R19: n_steps steps with the coarse transport and the chemistry on the
+ * children of the refined cells.  src_child[n_src]: child index of each source
+ * whose host cell is refined (ignored otherwise).  Returns -1 for bad
+ * arguments (ratio not 2 or 4, a refined cell out of range or repeated). */
+int oracle_run_crta(const int *ints, const double *dbls, const double *groups, int n_steps,
+                    double *N, double *F, double *x, double *T, const double *n0,
+                    const int64_t *src_cell, const double *src_rate, const int *src_child, int n_src,
+                    int n_ref, const int64_t *ref_cell, int ratio, double *xf, double *Tf, const double *nf,
+                    int64_t *counters) {
+    Params p;
+    if (!fill_params(p, ints, dbls, groups)) return -1;
+    if (ratio != 2 && ratio != 4) return -1;
+    const int64_t V = (int64_t)p.nx * p.ny * p.nz;
+    const int nc = ratio * ratio * ratio;
+    std::vector<int> which((size_t)V, -1);
+    for (int j = 0; j < n_ref; ++j) {
+        if (ref_cell[j] < 0 || ref_cell[j] >= V || which[(size_t)ref_cell[j]] >= 0) return -1;
+        which[(size_t)ref_cell[j]] = j;
+    }
+    const int G = p.G;
+    std::vector<double> Sc((size_t)V * G, 0.0), Sf((size_t)n_ref * nc * G, 0.0);
+    const double vol = p.dx * p.dx * p.dx;
+    const double hf = p.dx / ratio;
+    const double volf = hf * hf * hf;
+    for (int s = 0; s < n_src; ++s) {
+        const int j = which[(size_t)src_cell[s]];
+        if (j < 0) {
+            for (int g = 0; g < G; ++g) Sc[(size_t)src_cell[s] * G + g] += src_rate[s] * p.frac[g] / vol;
+        } else {
+            const int c = src_child ? src_child[s] : 0;
+            if (c < 0 || c >= nc) return -1;
+            for (int g = 0; g < G; ++g) Sf[((size_t)j * nc + c) * G + g] += src_rate[s] * p.frac[g] / volf;
+        }
+    }
+    Counters cnt;
+    run_crta<double>(p, n_steps, N, F, x, T, n0, Sc, n_ref, ref_cell, ratio, xf, Tf, nf, Sf, cnt);
     export_counters(cnt, counters);
     return 0;
 }
