@@ -144,6 +144,35 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
                  const double *n_H, const int64_t *src_cell, const double *src_rate,
                  int32_t n_src, double dt, int32_t n_steps, emma_rt_diag *diag);
 
+/* emma_rt_step with static refinement: the coarse radiative transport
+ * approximation of Sec. 5.  The transport runs on the coarse grid only; each
+ * refined coarse cell has r^3 children (r = ratio, 2 or 4) with their own gas,
+ * whose chemistry runs with the parent's post-transport N, F injected
+ * (piecewise constant) and with their own sources; the parent then holds the
+ * children's mean N and F, the n_H-weighted mean x_HII and the (1 + x) n_H-
+ * weighted mean T (its photons, ionised atoms and internal energy are the
+ * children's; means are pairwise sums in child order, so children equal to
+ * the parent reproduce emma_rt_step on the split path exactly).
+ *   N, F, x_HII, T, n_H, src_cell, src_rate, dt, n_steps, diag: as emma_rt_step
+ *                   (x_HII, T of refined cells are overwritten by the means)
+ *   src_child       device int32 [n_src], child index of each source whose
+ *                   host cell is refined (ignored for other sources); NULL = 0
+ *   ref_cell        device int64 [n_ref], distinct refined coarse cells
+ *   x_fine, T_fine  device double [n_ref][ratio^3], read and written; child
+ *                   index (cz ratio + cy) ratio + cx within the parent
+ *   n_fine          device double [n_ref][ratio^3], read only
+ * Child sources have density rate * src_frac / (dx / ratio)^3.  The transport
+ * uses the split path's tiled kernel (fused and split paths) or the reference
+ * kernel (reference path).  Entries of ref_cell outside the grid or repeated,
+ * and source children outside 0..ratio^3-1, are ignored and reported as
+ * EINVAL when diag is given.  No adjoint.  Returns as emma_rt_step, and EINVAL
+ * for ratio not 2 or 4 or NULL arrays with n_ref > 0. */
+int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
+                      const double *n_H, const int64_t *src_cell, const double *src_rate,
+                      const int32_t *src_child, int32_t n_src, double dt, int32_t n_steps,
+                      const int64_t *ref_cell, int32_t n_ref, int32_t ratio,
+                      double *x_fine, double *T_fine, const double *n_fine, emma_rt_diag *diag);
+
 /* Vector-Jacobian product of n_steps steps (1 <= n_steps <= adjoint_max_steps),
  * the exact derivative of the discrete map computed by emma_rt_step along the
  * branches (substep lengths, halvings, clamps) that the forward run takes.

@@ -26,7 +26,7 @@ PATHS = {"fused": 0, "split": 1, "reference": 2}
 BCS = {"periodic": 0, "transmissive": 1, "reflective": 2, "inflow": 3}
 FLUXES = {"glf": 0, "hll": 1}
 
-EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_adjoint", "emma_rt_free",
+EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_crta", "emma_rt_step_adjoint", "emma_rt_free",
            "emma_rt_last_error", "emma_rt_group_constants", "emma_rt_scratch_bytes",
            "emma_rt_profile_enable", "emma_rt_profile_read")
 
@@ -88,6 +88,10 @@ def load():
     L.emma_rt_step.restype = ctypes.c_int
     L.emma_rt_step.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
                                ctypes.c_int32, ctypes.POINTER(emma_rt_diag)]
+    L.emma_rt_step_crta.restype = ctypes.c_int
+    L.emma_rt_step_crta.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_int32,
+                                    _vp, _vp, _vp, ctypes.POINTER(emma_rt_diag)]
     L.emma_rt_step_adjoint.restype = ctypes.c_int
     L.emma_rt_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -135,6 +139,16 @@ def emma_rt_init(cfg, stream_ptr):
     if rc != EMMA_RT_OK:
         raise EmmaError(rc, L.emma_rt_last_error(None).decode())
     return ctx
+
+
+def emma_rt_step_crta(ctx, N, F, x, T, n0, src_cell, src_rate, src_child, n_src, dt, n_steps, ref_cell, n_ref,
+                      ratio, x_fine, T_fine, n_fine, diag=None):
+    """Pointers are integers (device addresses, 0 = NULL); returns the status code."""
+    L = load()
+    return L.emma_rt_step_crta(ctx, _vp(N), _vp(F), _vp(x), _vp(T), _vp(n0), _vp(src_cell), _vp(src_rate),
+                               _vp(src_child), int(n_src), float(dt), int(n_steps), _vp(ref_cell), int(n_ref),
+                               int(ratio), _vp(x_fine), _vp(T_fine), _vp(n_fine),
+                               ctypes.byref(diag) if diag is not None else None)
 
 
 def emma_rt_step(ctx, N, F, x, T, n0, src_cell, src_rate, n_src, dt, n_steps, diag=None):

@@ -29,6 +29,7 @@ struct emma_rt_ctx {
     size_t elem;           // bytes per N/F element (4 or 8)
     void *Ns, *Fs;         // transport output / fused ping-pong (storage precision)
     uint32_t *mask;        // one bit per cell: cell hosts a source
+    uint32_t *refmask;     // one bit per cell: cell is refined (emma_rt_step_crta)
     int64_t mask_words;
     int64_t *sorted_cell;  // [EMMA_RT_MAX_SOURCES]
     int32_t *sorted_idx;
@@ -183,7 +184,7 @@ extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
     if (config_error(cfg)) return -1;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     int64_t b = field_bytes(cfg);                          // Ns + Fs
-    b += ((V + 31) / 32) * 4;                              // mask
+    b += 2 * ((V + 31) / 32) * 4;                          // source and refinement masks
     b += V * 4 + 64;                                       // chemistry work list
     b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
     b += kCntSlots * CNT_COUNT * 8;
@@ -197,6 +198,7 @@ static void release(emma_rt_ctx *c) {
     (void)hipFree(c->Ns);
     (void)hipFree(c->Fs);
     (void)hipFree(c->mask);
+    (void)hipFree(c->refmask);
     (void)hipFree(c->sorted_cell);
     (void)hipFree(c->sorted_idx);
     (void)hipFree(c->S);
@@ -248,6 +250,7 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
         {&c->Ns, (size_t)(G * V) * c->elem},
         {&c->Fs, (size_t)(3 * G * V) * c->elem},
         {(void **)&c->mask, (size_t)c->mask_words * 4},
+        {(void **)&c->refmask, (size_t)c->mask_words * 4},
         {(void **)&c->sorted_cell, (size_t)EMMA_RT_MAX_SOURCES * 8},
         {(void **)&c->sorted_idx, (size_t)EMMA_RT_MAX_SOURCES * 4},
         {(void **)&c->S, (size_t)EMMA_RT_MAX_SOURCES * G * 8},
@@ -389,10 +392,10 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
             Timed t(c, KID_CHEM);
             if (cp.otsa && !cp.isothermal)
                 hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N,
-                                   F, x, T, n0, V, src, gc, cp, c->cnt, wl);
+                                   F, x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)nullptr);
             else
                 hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs,
-                                   N, F, x, T, n0, V, src, gc, cp, c->cnt, wl);
+                                   N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)nullptr);
         }
         if (int e = check_launch(c, "k_chem")) return e;
         if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
@@ -435,6 +438,9 @@ static int diag_finish(emma_rt_ctx *c, const S *N, const S *F, const double *x, 
     d->nonfinite = (int64_t)cnt[CNT_NONFINITE];
     if (cnt[CNT_BADSRC]) return fail(c, EMMA_RT_EINVAL, "%llu source cell indices outside the grid were ignored",
                                      cnt[CNT_BADSRC]);
+    if (cnt[CNT_BADREF])
+        return fail(c, EMMA_RT_EINVAL, "%llu refined-cell entries (outside the grid or repeated) or source children "
+                    "outside 0..r^3-1 were ignored", cnt[CNT_BADREF]);
     if (d->nonfinite) return fail(c, EMMA_RT_ENONFINITE, "%lld cells hold NaN/Inf", (long long)d->nonfinite);
     if (d->cap_hits) return fail(c, EMMA_RT_ESUBSTEP, "substep guard fired in %lld cell-steps",
                                  (long long)d->cap_hits);
@@ -489,6 +495,150 @@ extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double 
         DISPATCH(4)
     }
 #undef DISPATCH
+    return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
+}
+
+// ------------------------------------------------- refined cells (Sec. 5)
+template <int G, typename S, bool DIAG, int NC>
+static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const double *n0, const double *rate,
+                      const int32_t *src_child, int n_src, double dt, int n_steps, const int64_t *ref_cell,
+                      int n_ref, double *xf, double *Tf, const double *nf) {
+    const Grid gr = c->grid;
+    const int64_t V = gr.V;
+    const int tb = 256;
+    const unsigned nblk = (unsigned)((V + tb - 1) / tb);
+    const GroupConsts gc = group_consts(c->cfg);
+    ChemParams cp;
+    cp.c = c->cfg.c_red;
+    cp.dt = dt;
+    cp.otsa = c->cfg.otsa;
+    cp.isothermal = c->cfg.isothermal;
+    cp.max_substeps = c->cfg.max_substeps;
+    const bool fast = cp.otsa && !cp.isothermal;
+    SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
+    const WorkList wl{c->work_count, c->work_cells};
+    S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
+    const S cr = (S)c->cfg.c_red;
+    const S lam = (S)(dt / c->cfg.dx);
+    const double hf = c->cfg.dx / (NC == 8 ? 2 : 4);
+    const double volf = hf * hf * hf;
+    const unsigned fblk = (unsigned)(((int64_t)n_ref * NC + tb - 1) / tb);
+    for (int s = 0; s < n_steps; ++s) {
+        {
+            Timed t(c, KID_TRANSPORT);
+            if (c->cfg.path != EMMA_RT_PATH_REFERENCE)
+                launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
+                                                   bounds_of<S>(c));
+            else if (c->cfg.flux == EMMA_RT_FLUX_HLL)
+                hipLaunchKernelGGL((k_transport<G, S, DIAG, false, true>), dim3(nblk), dim3(tb), 0, c->stream, N,
+                                   F, Ns, Fs, gr, cr, lam, c->cnt, bounds_of<S>(c));
+            else
+                hipLaunchKernelGGL((k_transport<G, S, DIAG>), dim3(nblk), dim3(tb), 0, c->stream, N, F, Ns, Fs, gr,
+                                   cr, lam, c->cnt, bounds_of<S>(c));
+        }
+        if (int e = check_launch(c, "transport")) return e;
+        if (int e = reset_worklist(c)) return e;
+        {
+            Timed t(c, KID_CHEM);
+            if (fast)
+                hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F, x,
+                                   T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)c->refmask);
+            else
+                hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F,
+                                   x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)c->refmask);
+        }
+        if (int e = check_launch(c, "k_chem")) return e;
+        if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
+        if (n_ref > 0) {
+            Timed t(c, KID_CRTA);
+            if (fast)
+                hipLaunchKernelGGL((k_crta_fine<G, S, DIAG, true, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ns, Fs,
+                                   N, F, x, T, V, ref_cell, n_ref, xf, Tf, nf, c->sorted_cell, c->sorted_idx, rate,
+                                   src_child, n_src, gc, cp, volf, c->cnt);
+            else
+                hipLaunchKernelGGL((k_crta_fine<G, S, DIAG, false, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ns,
+                                   Fs, N, F, x, T, V, ref_cell, n_ref, xf, Tf, nf, c->sorted_cell, c->sorted_idx,
+                                   rate, src_child, n_src, gc, cp, volf, c->cnt);
+            if (int e = check_launch(c, "k_crta_fine")) return e;
+        }
+    }
+    return EMMA_RT_OK;
+}
+
+template <int G, typename S>
+static int crta_typed(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const double *n0, const int64_t *cell,
+                      const double *rate, const int32_t *src_child, int n_src, double dt, int n_steps,
+                      const int64_t *ref_cell, int n_ref, int ratio, double *xf, double *Tf, const double *nf,
+                      emma_rt_diag *d) {
+    const int tb = 256;
+    if (d) {
+        hipLaunchKernelGGL(k_fill_u64, dim3((kCntSlots * CNT_COUNT + 255) / 256), dim3(256), 0, c->stream,
+                           c->cnt, (int)(kCntSlots * CNT_COUNT), 0ull);
+        if (int e = check_launch(c, "k_fill_u64")) return e;
+    }
+    if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((c->mask_words + tb - 1) / tb)), dim3(tb), 0, c->stream,
+                       c->refmask, c->mask_words, 0u);
+    if (int e = check_launch(c, "k_fill_u32 (refined mask)")) return e;
+    if (n_ref > 0) {
+        hipLaunchKernelGGL(k_mark_refined, dim3((n_ref + tb - 1) / tb), dim3(tb), 0, c->stream, ref_cell, n_ref,
+                           c->grid.V, c->refmask, c->cnt);
+        if (int e = check_launch(c, "k_mark_refined")) return e;
+    }
+    int e;
+    if (ratio == 2)
+        e = d ? crta_steps<G, S, true, 8>(c, N, F, x, T, n0, rate, src_child, n_src, dt, n_steps, ref_cell, n_ref,
+                                          xf, Tf, nf)
+              : crta_steps<G, S, false, 8>(c, N, F, x, T, n0, rate, src_child, n_src, dt, n_steps, ref_cell, n_ref,
+                                           xf, Tf, nf);
+    else
+        e = d ? crta_steps<G, S, true, 64>(c, N, F, x, T, n0, rate, src_child, n_src, dt, n_steps, ref_cell,
+                                           n_ref, xf, Tf, nf)
+              : crta_steps<G, S, false, 64>(c, N, F, x, T, n0, rate, src_child, n_src, dt, n_steps, ref_cell,
+                                            n_ref, xf, Tf, nf);
+    if (e) return e;
+    if (d) return diag_finish<G, S>(c, N, F, x, T, n0, d);
+    return EMMA_RT_OK;
+}
+
+extern "C" int emma_rt_step_crta(emma_rt_ctx *c, void *N, void *F, double *x, double *T, const double *n0,
+                                 const int64_t *cell, const double *rate, const int32_t *src_child, int32_t n_src,
+                                 double dt, int32_t n_steps, const int64_t *ref_cell, int32_t n_ref, int32_t ratio,
+                                 double *x_fine, double *T_fine, const double *n_fine, emma_rt_diag *d) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (!N || !F || !x || !T || !n0) return fail(c, EMMA_RT_EINVAL, "a field pointer is NULL");
+    if (n_src < 0 || n_src > EMMA_RT_MAX_SOURCES)
+        return fail(c, EMMA_RT_EINVAL, "n_src must be in 0..%d", EMMA_RT_MAX_SOURCES);
+    if (n_src > 0 && (!cell || !rate)) return fail(c, EMMA_RT_EINVAL, "source arrays are NULL");
+    if (n_steps < 0) return fail(c, EMMA_RT_EINVAL, "n_steps must be >= 0");
+    if (!(dt > 0) || !isfinite(dt)) return fail(c, EMMA_RT_EINVAL, "dt must be > 0");
+    if (dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
+        return fail(c, EMMA_RT_EINVAL, "dt = %g exceeds dx/(3 c_red) = %g", dt, c->cfg.dx / (3.0 * c->cfg.c_red));
+    if (ratio != 2 && ratio != 4) return fail(c, EMMA_RT_EINVAL, "ratio must be 2 or 4");
+    if (n_ref < 0 || (int64_t)n_ref > c->grid.V) return fail(c, EMMA_RT_EINVAL, "n_ref must be in 0..cells");
+    if ((int64_t)n_ref * ratio * ratio * ratio > ((int64_t)1 << 31) - 256)
+        return fail(c, EMMA_RT_EINVAL, "too many children (n_ref * ratio^3)");
+    if (n_ref > 0 && (!ref_cell || !x_fine || !T_fine || !n_fine))
+        return fail(c, EMMA_RT_EINVAL, "refined-cell arrays are NULL");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
+    c->err[0] = 0;
+    const int G = c->cfg.n_groups;
+    const bool f64 = c->cfg.precision == EMMA_RT_FP64;
+#define CDISPATCH(GG)                                                                                          \
+    case GG:                                                                                                   \
+        return f64 ? crta_typed<GG, double>(c, (double *)N, (double *)F, x, T, n0, cell, rate, src_child, n_src, \
+                                            dt, n_steps, ref_cell, n_ref, ratio, x_fine, T_fine, n_fine, d)      \
+                   : crta_typed<GG, float>(c, (float *)N, (float *)F, x, T, n0, cell, rate, src_child, n_src,    \
+                                           dt, n_steps, ref_cell, n_ref, ratio, x_fine, T_fine, n_fine, d);
+    switch (G) {
+        CDISPATCH(1)
+        CDISPATCH(2)
+        CDISPATCH(3)
+        CDISPATCH(4)
+    }
+#undef CDISPATCH
     return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
 }
 
@@ -610,7 +760,8 @@ extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *
 // ------------------------------------------------------------ profiling
 static const char *kKindNames[KID_COUNT] = {"src_table", "transport", "chemistry", "fused_step",
                                             "diagnostics", "adj_chemistry", "adj_transport",
-                                            "adj_sources", "adj_forward", "chemistry_deferred"};
+                                            "adj_sources", "adj_forward", "chemistry_deferred",
+                                            "chemistry_refined"};
 
 extern "C" int emma_rt_profile_enable(emma_rt_ctx *c, int32_t enable) {
     if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");

@@ -33,6 +33,7 @@ enum Counter {
     CNT_ATT,
     CNT_NONFINITE,
     CNT_BADSRC,
+    CNT_BADREF,   // refined-cell list entries out of range or repeated, bad source children
     CNT_MAXSUB,   // max, via atomicMax
     CNT_COUNT
 };
@@ -49,6 +50,7 @@ enum KernelKind {
     KID_ADJ_SRC,
     KID_ADJ_FWD,
     KID_CHEM_LIST,
+    KID_CRTA,
     KID_COUNT
 };
 
@@ -384,11 +386,14 @@ __global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S 
                                               double *__restrict__ x, double *__restrict__ T,
                                               const double *__restrict__ n0, int64_t V,
                                               SrcTable src, GroupConsts gc, ChemParams cp,
-                                              unsigned long long *cnt, WorkList wl) {
+                                              unsigned long long *cnt, WorkList wl,
+                                              const uint32_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ChemStats st{0, 0, 0, 0};
     bool deferred = false;
-    if (i < V) {
+    // skip: one bit per cell, set for the refined cells whose children run
+    // the chemistry instead (null: every cell)
+    if (i < V && !(skip && ((skip[i >> 5] >> (i & 31)) & 1u))) {
         double Nc[G], Fc[G][3], Sc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -511,6 +516,129 @@ __global__ __launch_bounds__(256) void k_diag_partial(const S *N, const S *F, co
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int q = 0; q < G + 1; ++q) partial[(int64_t)blockIdx.x * (G + 1) + q] = sh[q][0];
+    }
+}
+
+// ------------------------------------------------- refined cells (Sec. 5)
+// The coarse radiative transport approximation with static refinement: the
+// transport runs on the coarse grid only; a refined coarse cell carries
+// NC = r^3 children with their own gas, whose chemistry runs with the
+// parent's post-transport radiation injected (piecewise constant); the
+// parent then holds the children's mean N, F, the n0-weighted mean x and the
+// (1 + x) n0-weighted mean T (its photons, ionised atoms and internal energy
+// are the children's).  Means are pairwise sums over the children in index
+// order, ((c0 + c1) + (c2 + c3)) + ..., so equal children give the parent
+// exactly.
+
+// Marks the refined cells in a one-bit-per-cell mask (cleared beforehand);
+// entries outside the grid or repeated are counted and ignored.
+__global__ void k_mark_refined(const int64_t *__restrict__ cell, int n, int64_t V, uint32_t *mask,
+                               unsigned long long *cnt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t bad = 0;
+    if (j < n) {
+        const int64_t p = cell[j];
+        if (p < 0 || p >= V) {
+            bad = 1;
+        } else {
+            const uint32_t bit = 1u << (p & 31);
+            if (atomicOr(mask + (p >> 5), bit) & bit) bad = 1;
+        }
+    }
+    wave_count(cnt, CNT_BADREF, bad);
+}
+
+// Pairwise sum over the NC consecutive lanes of one parent (NC divides 64):
+// after the step with mask m each lane holds the sum of its aligned block of
+// 2m lanes, added as (lower half) + (upper half) up to commutation.
+template <int NC>
+__device__ __forceinline__ double child_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < NC; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// One lane per child: chemistry on the injected radiation, then the
+// restriction; lane 0 of each parent writes the parent.  Children's sources:
+// the parent's sources (sorted table, list order) whose child index is this
+// lane's, at rate * frac / volf, volf = (dx / r)^3.
+template <int G, typename S, bool DIAG, bool FAST, int NC>
+__global__ __launch_bounds__(256) void k_crta_fine(const S *__restrict__ Ns, const S *__restrict__ Fs,
+                                                   S *__restrict__ N, S *__restrict__ F, double *__restrict__ x,
+                                                   double *__restrict__ T, int64_t V,
+                                                   const int64_t *__restrict__ ref_cell, int n_ref,
+                                                   double *__restrict__ xf, double *__restrict__ Tf,
+                                                   const double *__restrict__ nf,
+                                                   const int64_t *__restrict__ sorted_cell,
+                                                   const int32_t *__restrict__ sorted_idx,
+                                                   const double *__restrict__ rate,
+                                                   const int32_t *__restrict__ src_child, int n_src,
+                                                   GroupConsts gc, ChemParams cp, double volf,
+                                                   unsigned long long *cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = t / NC;
+    const int ch = (int)(t % NC);
+    ChemStats st{0, 0, 0, 0};
+    int64_t bad = 0;
+    const int64_t p = j < n_ref ? ref_cell[j] : -1;
+    // every lane of a parent agrees on `live`, so the sums stay inside live lanes
+    if (p >= 0 && p < V) {
+        double Nc[G], Fc[G][3], Sc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            Nc[g] = (double)Ns[(int64_t)g * V + p];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fc[g][k] = (double)Fs[((int64_t)g * 3 + k) * V + p];
+            Sc[g] = 0.0;
+        }
+        if (n_src > 0) {
+            for (int r = lower_bound_cell(sorted_cell, n_src, p); r < n_src && sorted_cell[r] == p; ++r) {
+                const int s = sorted_idx[r];
+                const int sc = src_child ? src_child[s] : 0;
+                if (sc == ch) {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) Sc[g] += rate[s] * gc.frac[g] / volf;
+                }
+                if (ch == 0 && (sc < 0 || sc >= NC)) bad++;
+            }
+        }
+        const int64_t f = j * NC + ch;
+        double xc = xf[f], Tc = Tf[f];
+        const double nc = nf[f];
+        st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, nc, Sc);
+        xf[f] = xc;
+        Tf[f] = Tc;
+        const double inv = 1.0 / NC;
+        double No[G], Fo[G][3];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            No[g] = child_sum<NC>(Nc[g]) * inv;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fo[g][k] = child_sum<NC>(Fc[g][k]) * inv;
+        }
+        const double nsum = child_sum<NC>(nc);
+        const double xp = child_sum<NC>(xc * (nc / nsum));
+        const double w = (1.0 + xc) * nc;
+        const double msum = child_sum<NC>(w);
+        const double Tp = child_sum<NC>(Tc * (w / msum));
+        if (ch == 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                N[(int64_t)g * V + p] = (S)No[g];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + p] = (S)Fo[g][k];
+            }
+            x[p] = xp;
+            T[p] = Tp;
+        }
+    }
+    wave_count(cnt, CNT_BADREF, bad);
+    if (DIAG) {
+        wave_count(cnt, CNT_SUB, st.substeps);
+        wave_count(cnt, CNT_ATT, st.attempts);
+        wave_count(cnt, CNT_CAP, st.cap);
+        wave_count(cnt, CNT_XCLAMP, st.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, st.substeps);
     }
 }
 

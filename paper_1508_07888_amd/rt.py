@@ -160,6 +160,35 @@ class EmmaRT:
             return out
         return rc
 
+    def step_crta(self, N, F, x, T, n0, src_cell, src_rate, dt, ref_cell, ratio, x_fine, T_fine, n_fine,
+                  n_steps=1, src_child=None, diag=False, raise_on_status=True):
+        """Steps with static refinement (coarse transport, chemistry on the
+        children of the refined cells; Sec. 5).  ref_cell int64 [n_ref];
+        x_fine, T_fine (updated in place), n_fine float64 [n_ref, ratio^3];
+        src_child int32 [n_src] (child of each source in a refined cell)."""
+        pN, pF, px, pT, pn = self._fields(N, F, x, T, n0)
+        n, pc, pr = self._sources(src_cell, src_rate)
+        pch = self._check(src_child, "src_child", torch.int32, (n,)) if (n and src_child is not None) else 0
+        n_ref = int(ref_cell.numel())
+        nc = int(ratio) ** 3
+        if n_ref:
+            pref = self._check(ref_cell, "ref_cell", torch.int64, (n_ref,))
+            pxf = self._check(x_fine, "x_fine", torch.float64, (n_ref, nc))
+            pTf = self._check(T_fine, "T_fine", torch.float64, (n_ref, nc))
+            pnf = self._check(n_fine, "n_fine", torch.float64, (n_ref, nc))
+        else:
+            pref = pxf = pTf = pnf = 0
+        d = _lib.emma_rt_diag() if diag else None
+        rc = _lib.emma_rt_step_crta(self._ctx, pN, pF, px, pT, pn, pc, pr, pch, n, dt, n_steps, pref, n_ref,
+                                    int(ratio), pxf, pTf, pnf, d)
+        if rc != _lib.EMMA_RT_OK and raise_on_status:
+            raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))
+        if diag:
+            out = d.as_dict(self.G)
+            out["status"] = rc
+            return out
+        return rc
+
     def step_adjoint(self, N0, F0, x0, T0, n0, src_cell, src_rate, dt, n_steps, gN, gF, gx, gT,
                      g_n0, g_rate):
         """In place: (gN, gF, gx, gT) from dL/d(end state) to dL/d(start state);
