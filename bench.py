@@ -156,7 +156,7 @@ def summarize_trace(trace_dir, out_path, command):
     return out_path
 
 
-def run_gpu(w, precision, steps, warmup, path="fused"):
+def run_gpu(w, precision, steps, warmup, path="split"):
     import torch
     from paper_1508_07888_amd import EmmaRT
     dev = "cuda:0"
@@ -222,7 +222,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--path", default="fused", choices=["fused", "split", "reference"],
+    ap.add_argument("--path", default="split", choices=["split", "fused", "reference"],
                     help="kernel path (all compute the same step; fused is the product path)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling rocprofv3 byte counters)")

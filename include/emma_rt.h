@@ -52,7 +52,7 @@ typedef enum {
 } emma_rt_status;
 
 typedef enum { EMMA_RT_FP64 = 0, EMMA_RT_MIXED = 1 } emma_rt_precision;
-typedef enum { EMMA_RT_PATH_FUSED = 0, EMMA_RT_PATH_SPLIT = 1, EMMA_RT_PATH_REFERENCE = 2 } emma_rt_path;
+typedef enum { EMMA_RT_PATH_SPLIT = 0, EMMA_RT_PATH_FUSED = 1, EMMA_RT_PATH_REFERENCE = 2 } emma_rt_path;
 /* Global boundary of one face (Sec. 4, gather step; Sec. 6 test set-ups).
  * Across a non-periodic face the outside neighbour of a boundary cell is:
  *   TRANSMISSIVE  the cell itself;
@@ -88,8 +88,10 @@ typedef struct {
                                    guard takes one last substep of the remainder */
     int32_t adjoint_max_steps;  /* K: longest segment emma_rt_step_adjoint accepts;
                                    0 = no adjoint scratch */
-    int32_t path;               /* kernels of the step: EMMA_RT_PATH_FUSED (default),
-                                   _SPLIT (tiled transport, then chemistry) or
+    int32_t path;               /* kernels of the step: EMMA_RT_PATH_SPLIT (default:
+                                   tiled transport, then chemistry), _FUSED (one
+                                   kernel, chemistry on the transport's registers:
+                                   one pass over HBM but fewer waves per SIMD) or
                                    _REFERENCE (one-cell-per-thread transport, then
                                    chemistry); all compute the same step */
     /* Per-group constants (Sec. 2.2.3-2.2.4, eq. e:siggroup and the sigma_E and

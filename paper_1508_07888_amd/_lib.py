@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESUBSTEP",
 
 EMMA_RT_FP64 = 0
 EMMA_RT_MIXED = 1
-PATHS = {"fused": 0, "split": 1, "reference": 2}
+PATHS = {"split": 0, "fused": 1, "reference": 2}
 BCS = {"periodic": 0, "transmissive": 1, "reflective": 2, "inflow": 3}
 FLUXES = {"glf": 0, "hll": 1}
 

@@ -148,7 +148,7 @@ static const char *config_error(const emma_rt_config *cfg) {
     if (cfg->precision != EMMA_RT_FP64 && cfg->precision != EMMA_RT_MIXED) return "bad precision";
     if (cfg->max_substeps < 1) return "max_substeps must be >= 1";
     if (cfg->adjoint_max_steps < 0) return "adjoint_max_steps must be >= 0";
-    if (cfg->path < EMMA_RT_PATH_FUSED || cfg->path > EMMA_RT_PATH_REFERENCE) return "bad path";
+    if (cfg->path < EMMA_RT_PATH_SPLIT || cfg->path > EMMA_RT_PATH_REFERENCE) return "bad path";
     for (int d = 0; d < 3; ++d) {
         const int a = cfg->bc[2 * d], b = cfg->bc[2 * d + 1];
         if (a < EMMA_RT_BC_PERIODIC || a > EMMA_RT_BC_INFLOW || b < EMMA_RT_BC_PERIODIC || b > EMMA_RT_BC_INFLOW)
@@ -324,6 +324,19 @@ static int launch_chem_list(emma_rt_ctx *c, const S *inN, const S *inF, S *oN, S
     return check_launch(c, "k_chem_list");
 }
 
+// First chemistry pass over every cell (skip: refined cells, or null).
+template <int G, typename S, bool DIAG, bool FAST>
+static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, double *x, double *T,
+                       const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp,
+                       const uint32_t *skip) {
+    const int64_t V = c->grid.V;
+    const WorkList wl{c->work_count, c->work_cells};
+    const int tb = 256;
+    hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST>), dim3((unsigned)((V + tb - 1) / tb)), dim3(tb), 0, c->stream, Ns,
+                       Fs, N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, skip);
+    return check_launch(c, "chemistry");
+}
+
 static int reset_worklist(emma_rt_ctx *c) {
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->work_count, (int64_t)1, 0u);
     return check_launch(c, "k_fill_u32 (work list)");
@@ -390,14 +403,11 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
         if (int e = reset_worklist(c)) return e;
         {
             Timed t(c, KID_CHEM);
-            if (cp.otsa && !cp.isothermal)
-                hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N,
-                                   F, x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)nullptr);
-            else
-                hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs,
-                                   N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)nullptr);
+            const int e = (cp.otsa && !cp.isothermal)
+                              ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, nullptr)
+                              : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, nullptr);
+            if (e) return e;
         }
-        if (int e = check_launch(c, "k_chem")) return e;
         if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
     }
     return EMMA_RT_OK;
@@ -516,7 +526,6 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
     cp.max_substeps = c->cfg.max_substeps;
     const bool fast = cp.otsa && !cp.isothermal;
     SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
-    const WorkList wl{c->work_count, c->work_cells};
     S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
     const S cr = (S)c->cfg.c_red;
     const S lam = (S)(dt / c->cfg.dx);
@@ -540,14 +549,10 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
         if (int e = reset_worklist(c)) return e;
         {
             Timed t(c, KID_CHEM);
-            if (fast)
-                hipLaunchKernelGGL((k_chem<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F, x,
-                                   T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)c->refmask);
-            else
-                hipLaunchKernelGGL((k_chem<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, Ns, Fs, N, F,
-                                   x, T, n0, V, src, gc, cp, c->cnt, wl, (const uint32_t *)c->refmask);
+            const int e = fast ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, c->refmask)
+                               : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, c->refmask);
+            if (e) return e;
         }
-        if (int e = check_launch(c, "k_chem")) return e;
         if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
         if (n_ref > 0) {
             Timed t(c, KID_CRTA);

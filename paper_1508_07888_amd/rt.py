@@ -32,7 +32,7 @@ class EmmaRT:
 
     def __init__(self, shape, n_groups, dx, c_red, precision="mixed", groups=None, T_bb=1e5,
                  edges_eV=None, otsa=True, isothermal=False, max_substeps=100000,
-                 adjoint_max_steps=0, path="fused", device="cuda:0", bc=None, inflow=None,
+                 adjoint_max_steps=0, path="split", device="cuda:0", bc=None, inflow=None,
                  flux="glf"):
         nz, ny, nx = shape
         self.shape = (nz, ny, nx)

@@ -15,7 +15,7 @@ def to_dev(a, dtype=torch.float64):
 
 
 def run_gpu(N, F, x, T, n0, cells, rates, *, dx, c_red, dt, n_steps, groups, precision="fp64",
-            otsa=1, isothermal=0, max_substeps=100000, diag=True, rt=None, path="fused", bc=None,
+            otsa=1, isothermal=0, max_substeps=100000, diag=True, rt=None, path="split", bc=None,
             inflow=None, flux="glf"):
     G = N.shape[0]
     own = rt is None

@@ -1,6 +1,6 @@
-"""The full-size workloads in the benchmark's launch configuration (fused
-path, one emma_rt_step call, no diagnostics), checked against the oracle on
-sampled cells.
+"""The full-size workloads in the benchmark's launch configuration (default
+split path, one emma_rt_step call, no diagnostics; the fused path too for the
+sampled 256^3 check), checked against the oracle on sampled cells.
 
 After k steps a cell depends only on the cells within k face-neighbour hops
 (radius-1 stencil, sources injected in their own cell), so the oracle run for
@@ -28,15 +28,15 @@ from sampling import block as _block, coords as _coords, hops_to_sources as _hop
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
-def _gpu_run(w, precision, steps, groups=None):
+def _gpu_run(w, precision, steps, groups=None, path="split"):
     from paper_1508_07888_amd import EmmaRT
     G = w["G"]
-    if groups is None:  # exactly the benchmark's context
+    if groups is None:  # exactly the benchmark's context (default path)
         rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"],
-                    edges_eV=w["edges"], path="fused", device=DEV)
+                    edges_eV=w["edges"], path=path, device=DEV)
     else:
         rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, groups=groups,
-                    path="fused", device=DEV)
+                    path=path, device=DEV)
     fdt = rt.dtype
     N, F = to_dev(w["N"], fdt), to_dev(w["F"], fdt)
     x, T, n0 = to_dev(w["x"]), to_dev(w["T"]), to_dev(w["n0"])
@@ -134,12 +134,13 @@ def w256():
     return E.make_workload("throughput256")
 
 
+@pytest.mark.parametrize("path", ["split", "fused"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_throughput256_sampled_cells(w256, precision):
+def test_throughput256_sampled_cells(w256, precision, path):
     steps = 8
     groups = None if precision == "mixed" else groups_for(w256["G"])
-    gpu = _gpu_run(w256, precision, steps, groups)
-    _sample_compare(w256, gpu, _samples(w256, 16, 1), steps, precision, "256^3")
+    gpu = _gpu_run(w256, precision, steps, groups, path)
+    _sample_compare(w256, gpu, _samples(w256, 16, 1), steps, precision, f"256^3 {path}")
 
 
 def test_throughput256_benchmark_run(w256):
@@ -166,7 +167,7 @@ def test_large512_forward_and_adjoint():
     # the oracle's dual-number tangent of that cell's x on the block
     shape, G = w["shape"], w["G"]
     rt = EmmaRT(shape, G, w["dx"], w["c_red"], precision="mixed", T_bb=w["T_bb"],
-                edges_eV=w["edges"], adjoint_max_steps=K, path="fused", device=DEV)
+                edges_eV=w["edges"], adjoint_max_steps=K, device=DEV)
     r = K + 1
     src = np.unique(w["src_cell"])
     chosen = []
