@@ -137,6 +137,32 @@ def summarize_pmc(fetch_dir, write_dir, workload, precision, out_dir, command):
     return written
 
 
+def summarize_sq(sq_dir, out_path, command):
+    """Short text summary of a rocprofv3 --pmc run of SQ counters: per kernel,
+    the mean per dispatch and the VALU / memory instructions per wave."""
+    import glob
+    f = glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True)[0]
+    agg = {}
+    for r in _kernel_rows(f):
+        kind, product = _kind(r["Kernel_Name"])
+        if not kind:
+            continue
+        name = r["Kernel_Name"].split("(")[0].replace("|", "/")
+        agg.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# rocprofv3 SQ counters (mean per dispatch)", "", f"command: `{command}`", "",
+             "| kernel | waves | VALU instr / wave | VMEM instr / wave | LDS instr / wave | wave cycles / wave |",
+             "|---|---|---|---|---|---|"]
+    for name, d in sorted(agg.items()):
+        m = {c: sum(v) / len(v) for c, v in d.items()}
+        w = max(m.get("SQ_WAVES", 0.0), 1.0)
+        lines.append(f"| {name} | {m.get('SQ_WAVES', 0):.0f} | {m.get('SQ_INSTS_VALU', 0) / w:.1f} | "
+                     f"{m.get('SQ_INSTS_VMEM', 0) / w:.1f} | {m.get('SQ_INSTS_LDS', 0) / w:.1f} | "
+                     f"{m.get('SQ_WAVE_CYCLES', 0) / w:.0f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return out_path
+
+
 def summarize_trace(trace_dir, out_path, command):
     """Short text summary of rocprofv3 --kernel-trace --stats (kernel stats CSV)."""
     import glob
@@ -228,6 +254,8 @@ def main():
                     help="also run a 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/*_pmc.json from two rocprofv3 --pmc output dirs and exit")
+    ap.add_argument("--summarize-sq", metavar="SQ_DIR",
+                    help="write a text summary of a rocprofv3 --pmc SQ_* run to --summary-out and exit")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR",
                     help="write a profiles/ text summary of a rocprofv3 --kernel-trace --stats dir and exit")
     ap.add_argument("--summary-out", default=None,
@@ -238,6 +266,9 @@ def main():
         out = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, "mixed",
                             args.summary_out or os.path.join(ROOT, "profiles"), args.command)
         print("\n".join(out))
+        return
+    if args.summarize_sq:
+        print(summarize_sq(args.summarize_sq, args.summary_out, args.command))
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.summary_out, args.command))
