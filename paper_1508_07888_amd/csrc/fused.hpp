@@ -105,9 +105,15 @@ __device__ __forceinline__ Vec4<R> ghost4(const Bounds<R> &b, int face, int g, R
 }
 
 // The four x/y split vectors (times 2) of one state with its closure.
+// The transport arithmetic here, in az2/bz2, in the closure and in the update
+// is kept free of FMA contraction: whether the compiler fuses a product into
+// an add depends on the surrounding code, which differs between the first
+// plane of a z tile and the planes rolled through the window (and between the
+// split and fused kernels), and the result must not depend on the tiling.
 template <typename R>
 __device__ __forceinline__ void split_xy(const Vec4<R> &u, const R P[6], R c, Vec4<R> &Ax, Vec4<R> &Bx,
                                          Vec4<R> &Ay, Vec4<R> &By) {
+#pragma clang fp contract(off)
     const R cN = c * u.n, cFx = c * u.fx, cFy = c * u.fy, cFz = c * u.fz, cc = c * c;
     const R pxx = cc * P[0], pxy = cc * P[1], pxz = cc * P[2], pyy = cc * P[3], pyz = cc * P[4];
     Ax = Vec4<R>{u.fx + cN, pxx + cFx, pxy + cFy, pxz + cFz};
@@ -119,10 +125,12 @@ __device__ __forceinline__ void split_xy(const Vec4<R> &u, const R P[6], R c, Ve
 // A_z and B_z parts (times 2) of one state with its closure.
 template <typename R>
 __device__ __forceinline__ Vec4<R> az2(const Vec4<R> &u, const R P[6], R c) {
+#pragma clang fp contract(off)
     return Vec4<R>{u.fz + c * u.n, c * c * P[2] + c * u.fx, c * c * P[4] + c * u.fy, c * c * P[5] + c * u.fz};
 }
 template <typename R>
 __device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R P[6], R c) {
+#pragma clang fp contract(off)
     return Vec4<R>{c * u.n - u.fz, c * u.fx - c * c * P[2], c * u.fy - c * c * P[4], c * u.fz - c * c * P[5]};
 }
 
@@ -308,6 +316,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
             }
             __syncthreads();
             {
+#pragma clang fp contract(off)
                 const Vec4<R> aL = lAx[buf][ty][tx], bR = lBx[buf][ty][tx + 1];
                 const Vec4<R> aD = lAy[buf][ty][tx], bT = lBy[buf][ty][tx];
                 // sum of the six split vectors (times 2) minus 6 c U, times lam / 2

@@ -377,42 +377,77 @@ __device__ inline void defer_push(const WorkList &wl, bool defer, uint32_t i) {
     if (defer) wl.cells[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
 }
 
+// The first chemistry pass touches every element exactly once per step: its
+// loads and stores are marked non-temporal (streamed past the caches).
+#ifndef EMMA_CHEM_NT
+#define EMMA_CHEM_NT 1
+#endif
+// F enters the subcycle only through the product of the substeps' factors, so
+// it is read after the subcycle, which keeps it out of the registers the
+// subcycle needs (more waves per SIMD to overlap memory with the FP64 work).
+#ifndef EMMA_CHEM_F_LATE
+#define EMMA_CHEM_F_LATE 1
+#endif
+#ifndef EMMA_CHEM_MIN_BLOCKS
+#define EMMA_CHEM_MIN_BLOCKS 1
+#endif
+
+template <typename T>
+__device__ __forceinline__ T stream_ld(const T *p) {
+    if (EMMA_CHEM_NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <typename T>
+__device__ __forceinline__ void stream_st(T *p, T v) {
+    if (EMMA_CHEM_NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
 // gas state and the cell's source density; writes the end-of-step N, F, x, T,
-// or defers the cell (budget exhausted: nothing written).
+// or defers the cell (budget exhausted: nothing written).  F_out = F* Pf with
+// Pf the product of the substeps' factors, as in chem_cell.
 template <int G, typename S, bool DIAG, bool FAST>
-__global__ __launch_bounds__(256) void k_chem(const S *__restrict__ Ns, const S *__restrict__ Fs,
-                                              S *__restrict__ N, S *__restrict__ F,
-                                              double *__restrict__ x, double *__restrict__ T,
-                                              const double *__restrict__ n0, int64_t V,
-                                              SrcTable src, GroupConsts gc, ChemParams cp,
-                                              unsigned long long *cnt, WorkList wl,
-                                              const uint32_t *__restrict__ skip) {
+__global__ __launch_bounds__(256, EMMA_CHEM_MIN_BLOCKS) void k_chem(
+    const S *__restrict__ Ns, const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
+    double *__restrict__ x, double *__restrict__ T, const double *__restrict__ n0, int64_t V, SrcTable src,
+    GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, const uint32_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ChemStats st{0, 0, 0, 0};
     bool deferred = false;
     // skip: one bit per cell, set for the refined cells whose children run
     // the chemistry instead (null: every cell)
     if (i < V && !(skip && ((skip[i >> 5] >> (i & 31)) & 1u))) {
-        double Nc[G], Fc[G][3], Sc[G];
+        double Nc[G], Sc[G], Pf[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            Nc[g] = (double)Ns[(int64_t)g * V + i];
+        for (int g = 0; g < G; ++g) Nc[g] = (double)stream_ld(Ns + (int64_t)g * V + i);
+#if !EMMA_CHEM_F_LATE
+        S Fr[G][3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) Fc[g][k] = (double)Fs[((int64_t)g * 3 + k) * V + i];
-        }
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fr[g][k] = stream_ld(Fs + ((int64_t)g * 3 + k) * V + i);
+#endif
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
-        double xc = x[i], Tc = T[i];
-        st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, n0[i], Sc, kChemBudget, &deferred);
+        double xc = stream_ld(x + i), Tc = stream_ld(T + i);
+        st = chem_cell_nxt<G, FAST>(gc, cp, Nc, Pf, xc, Tc, stream_ld(n0 + i), Sc, kChemBudget, &deferred);
         if (!deferred) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                N[(int64_t)g * V + i] = (S)Nc[g];
+                stream_st(N + (int64_t)g * V + i, (S)Nc[g]);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) F[((int64_t)g * 3 + k) * V + i] = (S)Fc[g][k];
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t o = ((int64_t)g * 3 + k) * V + i;
+#if EMMA_CHEM_F_LATE
+                    const S f = stream_ld(Fs + o);
+#else
+                    const S f = Fr[g][k];
+#endif
+                    stream_st(F + o, (S)((double)f * Pf[g]));
+                }
             }
-            x[i] = xc;
-            T[i] = Tc;
+            stream_st(x + i, xc);
+            stream_st(T + i, Tc);
         } else {
             st = ChemStats{0, 0, 0, 0};
         }

@@ -66,6 +66,7 @@ template <> struct FastMath<double> {
 // P = N g g^T / q.
 template <typename R>
 __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) {
+#pragma clang fp contract(off)
     using M = FastMath<R>;
     R a = N * R(1.0 / 3.0), k = R(0);  // chi = 1/3 when N <= 0
     R gx = R(0), gy = R(0), gz = R(0);
