@@ -81,18 +81,20 @@ def _kernel_rows(csv_path):
         return list(csv.DictReader(fh))
 
 
-def _kind(name):
-    """Kernel kind and whether it is the diagnostics-free instantiation."""
+def _kind(name, precision="mixed"):
+    """Kernel kind and whether it is the diagnostics-free instantiation of the
+    given precision's storage type (float: mixed, double: fp64)."""
     if "emma::" not in name or "<" not in name:
         return None, False
     targs = [t.strip() for t in name[name.index("<") + 1:name.index(">")].split(",")]
-    diag = len(targs) > 2 and targs[2] == "true"
+    storage = "float" if precision == "mixed" else "double"
+    product = not (len(targs) > 2 and targs[2] == "true") and len(targs) > 1 and targs[1] == storage
     if "k_tiled" in name:
-        return ("fused_step" if targs[3] == "true" else "transport"), not diag
+        return ("fused_step" if targs[3] == "true" else "transport"), product
     if "k_chem<" in name:
-        return "chemistry", not diag
+        return "chemistry", product
     if "k_transport<" in name:
-        return "transport", not diag
+        return "transport", product
     return None, False
 
 
@@ -110,11 +112,11 @@ def summarize_pmc(fetch_dir, write_dir, workload, precision, out_dir, command):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"]) * 1024.0
-            kind, product = _kind(r["Kernel_Name"])
+            kind, product = _kind(r["Kernel_Name"], precision)
             if kind and product:
                 per.setdefault(kind, []).append(v)
-            elif "emma::" not in r["Kernel_Name"] and v > COPY_BYTES / 4:
-                calib.append(v)
+            elif "MulFunctor" in r["Kernel_Name"] and v > COPY_BYTES / 4:
+                calib.append(v)  # the calibration kernel: torch.mul over 1 GiB
         if not calib:
             raise RuntimeError(f"no calibration kernel found in {f}")
         counters[counter] = (COPY_BYTES / max(calib), max(calib), {k: sum(v) / len(v) for k, v in per.items()})

@@ -154,18 +154,22 @@ def test_zero_steps_and_no_sources():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fused_and_split_paths_agree(precision):
-    # same transport arithmetic and the same chemistry code in both; the fused
-    # kernel only keeps N*, F* in registers between the two
-    k = _random_case((20, 12, 70), 3, 13)
+@pytest.mark.parametrize("shape", [(20, 12, 70), (33, 8, 64)])
+def test_fused_and_split_paths_agree_bitwise(precision, shape):
+    # Same transport arithmetic (free of FMA contraction, so the tiling does
+    # not matter) and the same chemistry code in both; the fused kernel only
+    # keeps N*, F* in registers between the two.  Ragged and whole tiles.
+    k = _random_case(shape, 3, 13)
     g = groups_for(3)
     kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=5, groups=g, precision=precision)
     a = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], path="fused", **kw)
     b = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], path="split", **kw)
-    tol = 1e-14 if precision == "fp64" else 1e-6
     for u, v in zip(a[:4], b[:4]):
-        assert normwise(u, v) <= tol
-    assert a[4]["substeps"] == b[4]["substeps"] and a[4]["limiter_hits"] == b[4]["limiter_hits"]
+        print(f"{shape} {precision}: max |fused - split| / max |split| = {normwise(u, v):.3e}", flush=True)
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+    for key in ("substeps", "attempts", "max_sub", "limiter_hits", "neg_clamps", "photons"):
+        assert a[4][key] == b[4][key], key
 
 
 def test_runs_are_bitwise_reproducible():
