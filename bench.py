@@ -8,14 +8,18 @@ P(k) ~ k^-2, seed 3), 256 point sources at random cells with log-uniform rates
 path: source table (once per call), transport of all groups, chemistry subcycle.
 
 Prints ONE JSON line: cell-updates/s of the FP32-transport / FP64-chemistry
-path (the metric), the all-FP64 path on the same inputs, the roofline figure of
-the dominant kernel (algorithmic bytes per launch over its event-timed average
-duration), and the CPU oracle timed on a bounded sample.
+path (the metric: the median of `--reps` calls of `--steps` steps, each from a
+fresh copy of the initial state, after `--warmup` untimed steps), the all-FP64
+path on the same inputs, the roofline figure of the dominant kernel
+(algorithmic bytes per launch over its average duration from HIP events in one
+more call of the same steps), the substep histogram, and the CPU oracle timed
+on a bounded sample.
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -184,7 +188,26 @@ def summarize_trace(trace_dir, out_path, command):
     return out_path
 
 
-def run_gpu(w, precision, steps, warmup, path="split"):
+def substep_hist_labels(hist):
+    """Cell-steps by accepted substeps, keyed by range: bit-length bins, "0",
+    "1", "2-3", "4-7", ..., the last open-ended."""
+    out = {}
+    for b, n in enumerate(hist):
+        if not n:
+            continue
+        if b == 0:
+            key = "0"
+        elif b == len(hist) - 1:
+            key = f"{1 << (b - 1)}+"
+        elif b == 1:
+            key = "1"
+        else:
+            key = f"{1 << (b - 1)}-{(1 << b) - 1}"
+        out[key] = n
+    return out
+
+
+def run_gpu(w, precision, steps, warmup, path="split", reps=5):
     import torch
     from paper_1508_07888_amd import EmmaRT
     dev = "cuda:0"
@@ -202,7 +225,8 @@ def run_gpu(w, precision, steps, warmup, path="split"):
     N, F, x, T = N0.clone(), F0.clone(), x0.clone(), T0.clone()
     if warmup > 0:
         rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=warmup)
-    # timed: K steps from the initial state, inputs resident in HBM
+    # K steps from the initial state, inputs resident in HBM, once with HIP
+    # events around every kernel (per-kernel durations for the roofline) ...
     N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
     rt.profile(True)
     rt.profile_read()
@@ -216,6 +240,17 @@ def run_gpu(w, precision, steps, warmup, path="split"):
     ms = start.elapsed_time(stop)
     kern = rt.profile_read()
     rt.profile(False)
+    # ... then `reps` times without them, each from a fresh copy of the initial
+    # state: the throughput is the median of these calls (min and max reported)
+    rep_ms = []
+    for _ in range(reps):
+        N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
+        torch.cuda.synchronize()
+        start.record(rt.stream)
+        rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=steps)
+        stop.record(rt.stream)
+        torch.cuda.synchronize()
+        rep_ms.append(start.elapsed_time(stop) / steps)
     # untimed diagnostic pass over the same steps (substep statistics)
     N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
     d = rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=steps, diag=True,
@@ -223,8 +258,15 @@ def run_gpu(w, precision, steps, warmup, path="split"):
     torch.cuda.synchronize()
     rt.close()
     V = N0[0].numel()
-    return dict(ms=ms, value=V * steps / (ms * 1e-3), ms_per_step=ms / steps, kernels=kern,
-                diag=d, V=V, elem=4 if precision == "mixed" else 8)
+    reps_out = None
+    per_step = ms / steps
+    if rep_ms:
+        per_step = statistics.median(rep_ms)
+        reps_out = {"count": len(rep_ms), "ms_per_step_median": per_step,
+                    "ms_per_step_min": min(rep_ms), "ms_per_step_max": max(rep_ms),
+                    "ms_per_step_with_kernel_events": ms / steps}
+    return dict(value=V / (per_step * 1e-3), ms_per_step=per_step, kernels=kern,
+                diag=d, V=V, elem=4 if precision == "mixed" else 8, reps=reps_out)
 
 
 def cpu_baseline(w, budget_steps=1):
@@ -250,6 +292,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--reps", type=int, default=5,
+                    help="further timed calls of the same steps from fresh copies (median, min, max)")
     ap.add_argument("--path", default="split", choices=["split", "fused", "reference"],
                     help="kernel path (all compute the same step; fused is the product path)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -285,8 +329,8 @@ def main():
     G = w["G"]
     if args.copy_calibration:
         copy_calibration()
-    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.path)
-    fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup, args.path)
+    mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.path, args.reps)
+    fp64 = None if args.no_fp64 else run_gpu(w, "fp64", args.steps, args.warmup, args.path, args.reps)
 
     kern = mixed["kernels"]
     dom = max((k for k in kern if k != "src_table"), key=lambda k: kern[k][1])
@@ -321,13 +365,15 @@ def main():
         "substeps_per_cell_step": mixed["diag"]["substeps"] / (mixed["V"] * args.steps),
         "attempts_per_cell_step": mixed["diag"]["attempts"] / (mixed["V"] * args.steps),
         "max_substeps_cell_step": mixed["diag"]["max_sub"],
+        "substep_hist": substep_hist_labels(mixed["diag"]["substep_hist"]),
+        "repetitions": mixed["reps"],
     }
     if fp64 is not None:
         k64 = fp64["kernels"]
         dom64 = max((k for k in k64 if k != "src_table"), key=lambda k: k64[k][1])
         b64 = algorithmic_bytes(dom64, G, 8) * fp64["V"]
         a64 = b64 / (k64[dom64][1] / k64[dom64][0] * 1e-3)
-        out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"],
+        out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "repetitions": fp64["reps"],
                        "dtype": "f64", "kernel": dom64, "achieved_GBs": a64 / 1e9,
                        "frac": a64 / HBM_PEAK,
                        "kernels_ms": {k: v[1] / v[0] for k, v in k64.items()}}

@@ -72,6 +72,7 @@ typedef enum {
 typedef enum { EMMA_RT_FLUX_GLF = 0, EMMA_RT_FLUX_HLL = 1 } emma_rt_flux;
 
 #define EMMA_RT_MAX_GROUPS 4
+#define EMMA_RT_SUBSTEP_BINS 18
 #define EMMA_RT_MAX_SOURCES 65536
 
 typedef struct {
@@ -122,6 +123,11 @@ typedef struct {
     int64_t x_clamps;                   /* chemistry: x_HII clamped to [0, 1] */
     int64_t cap_hits;                   /* chemistry: cells where the substep guard fired */
     int64_t nonfinite;                  /* cells with a NaN/Inf in the end state */
+    /* Histogram of accepted substeps per cell and step (refined cells: per
+       child), all steps of the call: bin 0 counts cell-steps with none (an
+       invalid energy leaves the cell untouched), bin k (1..16) those with
+       2^(k-1) <= n < 2^k, the last bin those with n >= 2^16. */
+    int64_t substep_hist[EMMA_RT_SUBSTEP_BINS];
 } emma_rt_diag;
 
 /* Create a context on the current HIP device.  cfg is copied.  hip_stream is a

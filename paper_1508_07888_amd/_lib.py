@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libemma_rt.so")
 
 MAX_GROUPS = 4
+SUBSTEP_BINS = 18  # EMMA_RT_SUBSTEP_BINS
 MAX_SOURCES = 65536
 
 EMMA_RT_OK = 0
@@ -53,6 +54,7 @@ class emma_rt_diag(ctypes.Structure):
         ("max_sub", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("limiter_hits", ctypes.c_int64), ("neg_clamps", ctypes.c_int64),
         ("x_clamps", ctypes.c_int64), ("cap_hits", ctypes.c_int64), ("nonfinite", ctypes.c_int64),
+        ("substep_hist", ctypes.c_int64 * SUBSTEP_BINS),
     ]
 
     def as_dict(self, G):
@@ -61,6 +63,7 @@ class emma_rt_diag(ctypes.Structure):
             "substeps": self.substeps, "attempts": self.attempts, "max_sub": self.max_sub,
             "limiter_hits": self.limiter_hits, "neg_clamps": self.neg_clamps,
             "x_clamps": self.x_clamps, "cap_hits": self.cap_hits, "nonfinite": self.nonfinite,
+            "substep_hist": list(self.substep_hist),
         }
 
 

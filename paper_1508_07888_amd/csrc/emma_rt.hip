@@ -446,6 +446,7 @@ static int diag_finish(emma_rt_ctx *c, const S *N, const S *F, const double *x, 
     d->x_clamps = (int64_t)cnt[CNT_XCLAMP];
     d->cap_hits = (int64_t)cnt[CNT_CAP];
     d->nonfinite = (int64_t)cnt[CNT_NONFINITE];
+    for (int b = 0; b < EMMA_RT_SUBSTEP_BINS; ++b) d->substep_hist[b] = (int64_t)cnt[CNT_HIST + b];
     if (cnt[CNT_BADSRC]) return fail(c, EMMA_RT_EINVAL, "%llu source cell indices outside the grid were ignored",
                                      cnt[CNT_BADSRC]);
     if (cnt[CNT_BADREF])

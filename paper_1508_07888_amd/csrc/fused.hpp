@@ -355,7 +355,8 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
         load_cell<G>(a.N, a.F, V, (zwrap(min(z + U, z1)) * plane + col) * E, cur);
         load_cell<G>(a.N, a.F, V, ((uint32_t)min(z + U, z1 - 1) * plane + hsrc) * E, hal);
 
-        bool deferred = false;
+        bool deferred = false, done = false;
+        int nsub = 0;
         if (FUSE && active) {
             double Nc[G], Sc[G], Pf[G];
 #pragma unroll
@@ -370,6 +371,8 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
                     tot.cap += cs.cap;
                     tot.xclamp += cs.xclamp;
                     maxsub = max(maxsub, cs.substeps);
+                    done = true;
+                    nsub = cs.substeps;
                 }
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
@@ -383,6 +386,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
             }
             // deferred: N*, F* go to the output below; x, T stay untouched
         }
+        if (DIAG && FUSE) wave_hist(a.cnt, done, nsub);
         if (active) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {

@@ -35,7 +35,8 @@ enum Counter {
     CNT_BADSRC,
     CNT_BADREF,   // refined-cell list entries out of range or repeated, bad source children
     CNT_MAXSUB,   // max, via atomicMax
-    CNT_COUNT
+    CNT_HIST,     // EMMA_RT_SUBSTEP_BINS counters: substeps per cell-step histogram
+    CNT_COUNT = CNT_HIST + EMMA_RT_SUBSTEP_BINS
 };
 
 // Kernel kinds for the per-kernel timing.
@@ -82,6 +83,26 @@ __device__ inline void wave_count(unsigned long long *cnt, int idx, int64_t v) {
 __device__ inline void wave_count_max(unsigned long long *cnt, int idx, int v) {
     v = wave_max(v);
     if ((threadIdx.x & 63) == 0 && v > 0) atomicMax(cnt_slot(cnt) + idx, (unsigned long long)v);
+}
+
+// Histogram bin of a cell-step with n accepted substeps: the bit length of n
+// (0 for none), everything from 2^16 in the last bin.
+__device__ inline int substep_bin(int n) {
+    const int b = n <= 0 ? 0 : 32 - __clz(n);
+    return b < EMMA_RT_SUBSTEP_BINS - 1 ? b : EMMA_RT_SUBSTEP_BINS - 1;
+}
+
+// Adds the lanes with `counted` set to the histogram bins of their substep
+// counts n, one atomic per bin present in the wave (all 64 lanes must call it).
+__device__ inline void wave_hist(unsigned long long *cnt, bool counted, int n) {
+    const int b = substep_bin(n);
+    unsigned long long todo = __ballot(counted);
+    while (todo) {  // wave-uniform: one pass per distinct bin
+        const int bl = __shfl(b, __ffsll((long long)todo) - 1, 64);
+        const unsigned long long m = __ballot(counted && b == bl);
+        if ((threadIdx.x & 63) == 0) atomicAdd(cnt_slot(cnt) + CNT_HIST + bl, (unsigned long long)__popcll(m));
+        todo &= ~m;
+    }
 }
 
 // ------------------------------------------------------------------ sources
@@ -414,7 +435,7 @@ __global__ __launch_bounds__(256, EMMA_CHEM_MIN_BLOCKS) void k_chem(
     GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, const uint32_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     ChemStats st{0, 0, 0, 0};
-    bool deferred = false;
+    bool deferred = false, done = false;
     // skip: one bit per cell, set for the refined cells whose children run
     // the chemistry instead (null: every cell)
     if (i < V && !(skip && ((skip[i >> 5] >> (i & 31)) & 1u))) {
@@ -448,6 +469,7 @@ __global__ __launch_bounds__(256, EMMA_CHEM_MIN_BLOCKS) void k_chem(
             }
             stream_st(x + i, xc);
             stream_st(T + i, Tc);
+            done = true;
         } else {
             st = ChemStats{0, 0, 0, 0};
         }
@@ -459,6 +481,7 @@ __global__ __launch_bounds__(256, EMMA_CHEM_MIN_BLOCKS) void k_chem(
         wave_count(cnt, CNT_CAP, st.cap);
         wave_count(cnt, CNT_XCLAMP, st.xclamp);
         wave_count_max(cnt, CNT_MAXSUB, st.substeps);
+        wave_hist(cnt, done, st.substeps);
     }
 }
 
@@ -500,6 +523,8 @@ __global__ __launch_bounds__(256) void k_chem_list(const S *Ns, const S *Fs, S *
             tot.cap += st.cap;
             tot.xclamp += st.xclamp;
             maxsub = max(maxsub, st.substeps);
+            // few cells reach this pass: one atomic each
+            atomicAdd(cnt_slot(cnt) + CNT_HIST + substep_bin(st.substeps), 1ull);
         }
     }
     if (DIAG) {
@@ -674,6 +699,7 @@ __global__ __launch_bounds__(256) void k_crta_fine(const S *__restrict__ Ns, con
         wave_count(cnt, CNT_CAP, st.cap);
         wave_count(cnt, CNT_XCLAMP, st.xclamp);
         wave_count_max(cnt, CNT_MAXSUB, st.substeps);
+        wave_hist(cnt, p >= 0 && p < V, st.substeps);
     }
 }
 

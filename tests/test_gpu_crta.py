@@ -76,6 +76,10 @@ def test_crta_matches_oracle(shape, G, ratio, seed, n_ref, precision, path):
     print(f"{shape} r={ratio} {precision} {path}: N {eN} F {eF} x {ex:.2e} T {eT:.2e} "
           f"children x {exf:.2e} T {eTf:.2e}", flush=True)
     assert r[6]["status"] == 0
+    # the substep histogram counts the coarse cells and, for a refined cell,
+    # its r^3 children instead, once per step
+    n_ref_cells = len(k["ref"])
+    assert sum(r[6]["substep_hist"]) == (k["n0"].size - n_ref_cells + n_ref_cells * ratio ** 3) * steps
     if precision == "fp64":
         assert max(eN) <= 1e-12 and max(eF) <= 1e-12
         assert max(ex, eT, exf, eTf) <= 1e-12
