@@ -269,6 +269,88 @@ def run_gpu(w, precision, steps, warmup, path="split", reps=5):
                 diag=d, V=V, elem=4 if precision == "mixed" else 8, reps=reps_out)
 
 
+def run_variants(w, steps=10, reps=3):
+    """The step's other kernel paths and options on the same inputs (mixed
+    precision, `steps` steps from the initial state, median of `reps` calls
+    after one warm-up step), next to the default split path over the same
+    steps: the fused and reference paths, the HLL flux with M1 wave speeds
+    (reference path), open boundaries with a planar inflow beam, the case-A
+    chemistry with recombination photons, and static refinement (chemistry on
+    the 2^3 children of the 4096 densest cells, emma_rt_step_crta)."""
+    import numpy as np
+    import torch
+    from paper_1508_07888_amd import EmmaRT
+    dev = "cuda:0"
+    G, V = w["G"], w["n0"].size
+    beam = float(w["c_red"] * 1e-6)  # inflow through z-: N = 1e-6 photons/cm^3 moving along +z
+    cases = {
+        "split": {},
+        "fused": dict(path="fused"),
+        "reference_glf": dict(path="reference"),
+        "reference_hll": dict(path="reference", flux="hll"),
+        "open_boundaries": dict(bc=["transmissive", "transmissive", "reflective", "reflective", "inflow",
+                                    "transmissive"], inflow=[0, 0, 0, 0, beam, 0]),
+        "case_a": dict(otsa=False),
+        "refined_cells": {},
+    }
+    n0 = torch.tensor(w["n0"], dtype=torch.float64, device=dev)
+    cells = torch.tensor(w["src_cell"], dtype=torch.int64, device=dev)
+    rates = torch.tensor(w["src_rate"], dtype=torch.float64, device=dev)
+    ref = np.sort(np.argsort(-w["n0"].ravel(), kind="stable")[:4096]).astype(np.int64)
+    child = np.zeros(w["src_cell"].size, np.int32)
+    out = {}
+    for name, kw in cases.items():
+        rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision="mixed", T_bb=w["T_bb"], edges_eV=w["edges"],
+                    device=dev, **kw)
+        N0 = torch.tensor(w["N"], dtype=rt.dtype, device=dev)
+        F0 = torch.tensor(w["F"], dtype=rt.dtype, device=dev)
+        x0 = torch.tensor(w["x"], dtype=torch.float64, device=dev)
+        T0 = torch.tensor(w["T"], dtype=torch.float64, device=dev)
+        N, F, x, T = N0.clone(), F0.clone(), x0.clone(), T0.clone()
+        if name == "refined_cells":
+            gref = torch.tensor(ref, dtype=torch.int64, device=dev)
+            nf0 = n0.reshape(-1)[gref].unsqueeze(1).repeat(1, 8).contiguous()
+            xf0 = x0.reshape(-1)[gref].unsqueeze(1).repeat(1, 8).contiguous()
+            Tf0 = T0.reshape(-1)[gref].unsqueeze(1).repeat(1, 8).contiguous()
+            xf, Tf = xf0.clone(), Tf0.clone()
+            gch = torch.tensor(child, dtype=torch.int32, device=dev)
+
+            def call(k):
+                rt.step_crta(N, F, x, T, n0, cells, rates, w["dt"], gref, 2, xf, Tf, nf0, n_steps=k,
+                             src_child=gch)
+
+            def reset():
+                N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0); xf.copy_(xf0); Tf.copy_(Tf0)
+        else:
+            def call(k):
+                rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=k)
+
+            def reset():
+                N.copy_(N0); F.copy_(F0); x.copy_(x0); T.copy_(T0)
+        call(1)
+        ms = []
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        for _ in range(reps):
+            reset()
+            torch.cuda.synchronize()
+            start.record(rt.stream)
+            call(steps)
+            stop.record(rt.stream)
+            torch.cuda.synchronize()
+            ms.append(start.elapsed_time(stop) / steps)
+        rt.close()
+        med = statistics.median(ms)
+        out[name] = {"ms_per_step": med, "cell_updates_per_s": V / (med * 1e-3), "vs_split": None}
+        del N0, F0, x0, T0, N, F, x, T
+        torch.cuda.empty_cache()
+    for name in out:
+        out[name]["vs_split"] = out["split"]["ms_per_step"] / out[name]["ms_per_step"]
+    out["steps"] = steps
+    out["refined_cells"]["n_ref"] = int(ref.size)
+    return out
+
+
 def cpu_baseline(w, budget_steps=1):
     """The oracle, untuned and serial, on the first step of the same inputs."""
     import oracle
@@ -292,6 +374,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time the other paths and options (fused, reference, HLL, open boundaries, "
+                         "case A, refined cells) over 10 steps of the same inputs")
     ap.add_argument("--reps", type=int, default=5,
                     help="further timed calls of the same steps from fresh copies (median, min, max)")
     ap.add_argument("--path", default="split", choices=["split", "fused", "reference"],
@@ -378,6 +463,8 @@ def main():
                        "frac": a64 / HBM_PEAK,
                        "kernels_ms": {k: v[1] / v[0] for k, v in k64.items()}}
         out["mixed_over_fp64"] = mixed["value"] / fp64["value"]
+    if args.variants:
+        out["variants"] = run_variants(w)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
