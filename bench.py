@@ -351,6 +351,74 @@ def run_variants(w, steps=10, reps=3):
     return out
 
 
+def run_adjoint(w, precision, K=10, reps=3):
+    """emma_rt_step_adjoint over K steps from the initial state (the segment's
+    forward recomputed into the tape, then the reverse sweep), loss = sum of
+    x_HII over the central 64^3 block: median of `reps` calls after one
+    warm-up call, per step of the segment."""
+    import torch
+    from paper_1508_07888_amd import EmmaRT
+    dev = "cuda:0"
+    G = w["G"]
+    rt = EmmaRT(w["shape"], G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"], edges_eV=w["edges"],
+                adjoint_max_steps=K, device=dev)
+    fdt = rt.dtype
+    N0 = torch.tensor(w["N"], dtype=fdt, device=dev)
+    F0 = torch.tensor(w["F"], dtype=fdt, device=dev)
+    x0 = torch.tensor(w["x"], dtype=torch.float64, device=dev)
+    T0 = torch.tensor(w["T"], dtype=torch.float64, device=dev)
+    n0 = torch.tensor(w["n0"], dtype=torch.float64, device=dev)
+    cells = torch.tensor(w["src_cell"], dtype=torch.int64, device=dev)
+    rates = torch.tensor(w["src_rate"], dtype=torch.float64, device=dev)
+    n = w["shape"][0]
+    lo, hi = n // 2 - 32, n // 2 + 32
+    gx0 = torch.zeros_like(x0)
+    gx0[lo:hi, lo:hi, lo:hi] = 1.0
+    gN, gF, gx, gT = torch.zeros_like(N0), torch.zeros_like(F0), gx0.clone(), torch.zeros_like(T0)
+    g_n0, g_rate = torch.zeros_like(n0), torch.zeros_like(rates)
+
+    def call():
+        gN.zero_(); gF.zero_(); gx.copy_(gx0); gT.zero_(); g_n0.zero_(); g_rate.zero_()
+        rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+
+    call()
+    rt.profile(True)
+    rt.profile_read()
+    call()
+    torch.cuda.synchronize()
+    kern = rt.profile_read()
+    rt.profile(False)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        start.record(rt.stream)
+        call()
+        stop.record(rt.stream)
+        torch.cuda.synchronize()
+        ms.append(start.elapsed_time(stop) / K)
+    finite = bool(torch.isfinite(g_n0).all().item() and torch.isfinite(g_rate).all().item())
+    rt.close()
+    med = statistics.median(ms)
+    return {"ms_per_step": med, "cell_steps_per_s": w["n0"].size / (med * 1e-3), "K": K,
+            "scratch_GB": rt_scratch_gb(w, precision, K), "gradients_finite": finite,
+            "kernels_ms_per_step": {k: v[1] / K for k, v in kern.items()}}
+
+
+def rt_scratch_gb(w, precision, K):
+    from paper_1508_07888_amd import _lib
+    cfg = _lib.emma_rt_config()
+    nz, ny, nx = w["shape"]
+    cfg.nx, cfg.ny, cfg.nz, cfg.n_groups = nx, ny, nz, w["G"]
+    cfg.dx, cfg.c_red = w["dx"], w["c_red"]
+    cfg.precision = _lib.EMMA_RT_MIXED if precision == "mixed" else _lib.EMMA_RT_FP64
+    cfg.otsa, cfg.max_substeps, cfg.adjoint_max_steps = 1, 100000, K
+    for g in range(w["G"]):
+        cfg.sigma_N[g] = cfg.sigma_E[g] = cfg.mean_E[g] = cfg.src_frac[g] = 1.0
+    return _lib.emma_rt_scratch_bytes(cfg) / 1e9
+
+
 def cpu_baseline(w, budget_steps=1):
     """The oracle, untuned and serial, on the first step of the same inputs."""
     import oracle
@@ -377,6 +445,8 @@ def main():
     ap.add_argument("--variants", action="store_true",
                     help="also time the other paths and options (fused, reference, HLL, open boundaries, "
                          "case A, refined cells) over 10 steps of the same inputs")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time emma_rt_step_adjoint over 10 steps (mixed and FP64)")
     ap.add_argument("--reps", type=int, default=5,
                     help="further timed calls of the same steps from fresh copies (median, min, max)")
     ap.add_argument("--path", default="split", choices=["split", "fused", "reference"],
@@ -465,6 +535,8 @@ def main():
         out["mixed_over_fp64"] = mixed["value"] / fp64["value"]
     if args.variants:
         out["variants"] = run_variants(w)
+    if args.adjoint:
+        out["adjoint"] = {p: run_adjoint(w, p) for p in (("mixed",) if args.no_fp64 else ("mixed", "fp64"))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -215,15 +215,21 @@ __host__ __device__ inline void substep_adj(const GroupConsts &gc, const ChemPar
 }
 
 // Reverse of chem_cell: inputs (N, F, x, T) of the subcycle and dL/d(outputs)
-// -> dL/d(inputs), dL/dn0, dL/dS.  The substep sequence is recomputed with
-// substep() from the cell's start for each substep in turn (cost quadratic in
-// the substep count of the cell, which is 1 or 2 for almost every cell).
-template <int G, bool FAST>
+// -> dL/d(inputs), dL/dn0, dL/dS.  The start state of each substep is
+// recomputed with substep() (identical decisions): from the cell's start when
+// M = 0 (cost quadratic in the cell's substep count K, which is 1 or 2 for
+// almost every cell), else from the nearest of M kept states, one every
+// s = ceil(K / M) substeps (a second forward pass keeps them; about
+// 2K + K s / 2 substeps in all).  Both give the same bits.  With a finite
+// budget the cell gives up when K exceeds it (*deferred = true, outputs
+// meaningless), so a caller can hand long subcycles to the kept-state form.
+template <int G, bool FAST, int M = 0>
 __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemParams &p, const double (&N0)[G],
                                      const double (&F0)[G][3], double x0, double T0, double n0,
                                      const double (&S)[G], const double (&aNo)[G], const double (&aFo)[G][3],
                                      double axo, double aTo, double (&aN)[G], double (&aF)[G][3], double &ax,
-                                     double &aT, double &an0, double (&aS)[G]) {
+                                     double &aT, double &an0, double (&aS)[G], int budget = 0x7fffffff,
+                                     bool *deferred = nullptr) {
     const bool iso = FAST ? false : (p.isothermal != 0);
     const double eunit = 1.5 * n0 * kKB;
     const double e0 = eunit * (1.0 + x0) * T0;
@@ -235,6 +241,10 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
     ChemStats st{0, 0, 0, 0};
     int K = 0;
     while (rem > 0.0) {
+        if (K >= budget) {
+            *deferred = true;
+            return;
+        }
         const bool last = K >= p.max_substeps;
         double inv[G];
         if (!substep<G, FAST>(gc, p, last, n0, eunit, T0, S, N, x, e, rem, inv, st, nullptr)) break;
@@ -242,6 +252,29 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
         for (int g = 0; g < G; ++g) Pf[g] *= inv[g];
         K++;
         if (last || iso) break;
+    }
+    // kept start states (M > 0): substeps 0, s, 2s, ...
+    constexpr int MK = M > 0 ? M : 1;
+    double kN[MK][G], kx[MK], ke[MK], kr[MK];
+    const int s = M > 0 ? (K + MK - 1) / MK : 0;
+    if (M > 0 && K > 0) {
+        double Ns[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) Ns[g] = N0[g];
+        double xs = x0, es = e0, rs = p.dt;
+        ChemStats st2{0, 0, 0, 0};
+        double inv[G];
+        for (int j = 0; j < K; ++j) {
+            if (j % s == 0) {
+                const int b = j / s;
+#pragma unroll
+                for (int g = 0; g < G; ++g) kN[b][g] = Ns[g];
+                kx[b] = xs;
+                ke[b] = es;
+                kr[b] = rs;
+            }
+            substep<G, FAST>(gc, p, j >= p.max_substeps, n0, eunit, T0, S, Ns, xs, es, rs, inv, st2, nullptr);
+        }
     }
     // F_out = F_in prod_k inv_k: dL/dinv_k (through F) = Phi_g / inv_k
     double Phi[G];
@@ -271,12 +304,27 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
     }
     for (int k = K - 1; k >= 0; --k) {
         double Ns[G];
+        double xs, es, rs;
+        int j0;
+        if (M > 0) {
+            const int b = k / s;
 #pragma unroll
-        for (int g = 0; g < G; ++g) Ns[g] = N0[g];
-        double xs = x0, es = e0, rs = p.dt;
+            for (int g = 0; g < G; ++g) Ns[g] = kN[b][g];
+            xs = kx[b];
+            es = ke[b];
+            rs = kr[b];
+            j0 = b * s;
+        } else {
+#pragma unroll
+            for (int g = 0; g < G; ++g) Ns[g] = N0[g];
+            xs = x0;
+            es = e0;
+            rs = p.dt;
+            j0 = 0;
+        }
         ChemStats st2{0, 0, 0, 0};
         double inv[G];
-        for (int j = 0; j < k; ++j)
+        for (int j = j0; j < k; ++j)
             substep<G, FAST>(gc, p, j >= p.max_substeps, n0, eunit, T0, S, Ns, xs, es, rs, inv, st2, nullptr);
         // decisions of substep k from its start state
         double Nk[G];
@@ -333,16 +381,28 @@ __host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, do
     if (floored) an = 0.0;
 }
 
-template <int G, typename S, bool FAST>
-__global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
-                                                  const double *__restrict__ xs, const double *__restrict__ Ts,
-                                                  const double *__restrict__ n0, int64_t V, SrcTable src,
-                                                  GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
-                                                  const S *__restrict__ gF, double *__restrict__ gx,
-                                                  double *__restrict__ gT, double *__restrict__ g_n0,
-                                                  double *__restrict__ gS, double *__restrict__ gU) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
+// Kept start states of the deferred-cell chemistry adjoint, per lane.
+#ifndef EMMA_ADJ_KEPT
+#define EMMA_ADJ_KEPT 32
+#endif
+// Substeps up to which the first chemistry-adjoint pass recomputes each
+// substep's start from the cell's start (at most budget (budget + 1) / 2
+// substeps); longer subcycles are deferred to the kept-state pass.
+#ifndef EMMA_ADJ_BUDGET
+#define EMMA_ADJ_BUDGET 4
+#endif
+
+// The chemistry adjoint of cell i (and the reverse of the floor and limiter
+// before it).  Returns false, with nothing written, when the cell's subcycle
+// exceeds the budget.
+template <int G, typename S, bool FAST, int M>
+__device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const S *__restrict__ Ft,
+                                     const double *__restrict__ xs, const double *__restrict__ Ts,
+                                     const double *__restrict__ n0, int64_t V, const SrcTable &src,
+                                     const GroupConsts &gc, const ChemParams &cp, const S *__restrict__ gN,
+                                     const S *__restrict__ gF, double *__restrict__ gx, double *__restrict__ gT,
+                                     double *__restrict__ g_n0, double *__restrict__ gS, double *__restrict__ gU,
+                                     int budget) {
     const double c = cp.c;
     double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], aNo[G], aFo[G][3], Sc[G];
 #pragma unroll
@@ -362,8 +422,10 @@ __global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, cons
     }
     source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
     double aN[G], aF[G][3], aS[G], ax, aT, an0;
-    chem_cell_adj<G, FAST>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i], aN, aF, ax, aT, an0,
-                           aS);
+    bool deferred = false;
+    chem_cell_adj<G, FAST, M>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i], aN, aF, ax, aT,
+                              an0, aS, budget, &deferred);
+    if (deferred) return false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, aN[g], aF[g][0], aF[g][1], aF[g][2]);
@@ -380,6 +442,44 @@ __global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, cons
 #pragma unroll
         for (int g = 0; g < G; ++g) gS[(int64_t)r * G + g] += aS[g];
     }
+    return true;
+}
+
+// First pass, one thread per cell: subcycles of at most EMMA_ADJ_BUDGET
+// substeps; longer ones are appended to the work list (a few wave-long
+// subcycles would otherwise hold their whole wave for their quadratic cost).
+template <int G, typename S, bool FAST>
+__global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
+                                                  const double *__restrict__ xs, const double *__restrict__ Ts,
+                                                  const double *__restrict__ n0, int64_t V, SrcTable src,
+                                                  GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
+                                                  const S *__restrict__ gF, double *__restrict__ gx,
+                                                  double *__restrict__ gT, double *__restrict__ g_n0,
+                                                  double *__restrict__ gS, double *__restrict__ gU, WorkList wl) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool deferred = false;
+    if (i < V)
+        deferred = !chem_adj_cell<G, S, FAST, 0>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
+                                                 gU, EMMA_ADJ_BUDGET);
+    defer_push(wl, deferred, (uint32_t)i);
+}
+
+// Second pass over the deferred cells (grid-stride over the list): every
+// substep's start recomputed from the nearest of EMMA_ADJ_KEPT kept states.
+template <int G, typename S, bool FAST>
+__global__ __launch_bounds__(256) void k_chem_adj_list(const S *__restrict__ Ut, const S *__restrict__ Ft,
+                                                       const double *__restrict__ xs, const double *__restrict__ Ts,
+                                                       const double *__restrict__ n0, int64_t V, SrcTable src,
+                                                       GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
+                                                       const S *__restrict__ gF, double *__restrict__ gx,
+                                                       double *__restrict__ gT, double *__restrict__ g_n0,
+                                                       double *__restrict__ gS, double *__restrict__ gU,
+                                                       WorkList wl) {
+    const uint32_t n = *wl.count;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        chem_adj_cell<G, S, FAST, EMMA_ADJ_KEPT>((int64_t)wl.cells[k], Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF,
+                                                 gx, gT, g_n0, gS, gU, 0x7fffffff);
 }
 
 // ------------------------------------------------------- transport adjoint

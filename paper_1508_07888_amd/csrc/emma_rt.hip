@@ -681,7 +681,7 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     HIP_TRY(c, hipMemcpyAsync(tT(0), T0, db, hipMemcpyDeviceToDevice, c->stream));
     for (int s = 0; s + 1 < n_steps; ++s) {
         HIP_TRY(c, hipMemcpyAsync(tN(s + 1), tN(s), (size_t)step_bytes, hipMemcpyDeviceToDevice, c->stream));
-        Timed t(c, KID_ADJ_FWD);
+        // (its kernels are timed under their own kinds: no bracket around a bracket)
         if (int e = run_steps<G, S, false>(c, tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1), n0, n_src, dt, 1))
             return e;
     }
@@ -699,16 +699,27 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
                                Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport (adjoint recompute)")) return e;
+        if (int e = reset_worklist(c)) return e;
         {
             Timed t(c, KID_ADJ_CHEM);
+            const WorkList wl{c->work_count, c->work_cells};
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
             else
                 hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
+            if (int e = check_launch(c, "k_chem_adj")) return e;
+            if (fast)
+                hipLaunchKernelGGL((k_chem_adj_list<G, S, true>), dim3(c->list_blocks), dim3(tb), 0, c->stream, Ut,
+                                   Ft, tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS,
+                                   c->adj.gU, wl);
+            else
+                hipLaunchKernelGGL((k_chem_adj_list<G, S, false>), dim3(c->list_blocks), dim3(tb), 0, c->stream, Ut,
+                                   Ft, tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS,
+                                   c->adj.gU, wl);
         }
-        if (int e = check_launch(c, "k_chem_adj")) return e;
+        if (int e = check_launch(c, "k_chem_adj_list")) return e;
         {
             Timed t(c, KID_ADJ_TRANSPORT);
             hipLaunchKernelGGL((k_transport_adj<G, S>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),

@@ -22,6 +22,7 @@ CSRC = os.path.join(ROOT, "paper_1508_07888_amd", "csrc")
 PROG = r'''
 #include "adjoint.hpp"
 #include <cstdio>
+#include <cstring>
 using namespace emma;
 template <int G> int run() {
     GroupConsts gc; ChemParams p;
@@ -39,12 +40,21 @@ template <int G> int run() {
         chem_cell_adj<G, false>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, aN, aF, ax, aT, an0, aS);
     for (int g = 0; g < G; ++g) printf("%.17g %.17g %.17g %.17g %.17g\n", aN[g], aF[g][0], aF[g][1], aF[g][2], aS[g]);
     printf("%.17g %.17g %.17g\n", ax, aT, an0);
+    // the kept-state form (3 kept states: several substeps per segment) gives the same bits
+    double bN[G], bF[G][3], bS[G], bx, bT, bn0;
+    if (p.otsa && !p.isothermal)
+        chem_cell_adj<G, true, 3>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
+    else
+        chem_cell_adj<G, false, 3>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
+    bool same = memcmp(&ax, &bx, 8) == 0 && memcmp(&aT, &bT, 8) == 0 && memcmp(&an0, &bn0, 8) == 0 &&
+                memcmp(aN, bN, sizeof aN) == 0 && memcmp(aF, bF, sizeof aF) == 0 && memcmp(aS, bS, sizeof aS) == 0;
     // forward value for a consistency check
     double N[G], F[G][3]; for (int g = 0; g < G; ++g) { N[g] = Nin[g]; for (int k = 0; k < 3; ++k) F[g][k] = Fin[g][k]; }
     double xx = x, TT = T;
     ChemStats st = (p.otsa && !p.isothermal) ? chem_cell<G, true>(gc, p, N, F, xx, TT, n0, S)
                                              : chem_cell<G, false>(gc, p, N, F, xx, TT, n0, S);
     printf("%.17g %.17g %d\n", xx, TT, st.substeps);
+    printf("%d\n", same ? 1 : 0);
     return 0;
 }
 int main() { int G; scanf("%d", &G); if (G == 1) return run<1>(); if (G == 2) return run<2>(); return run<3>(); }
@@ -98,6 +108,7 @@ def _run_adj(exe, G, g, c, dt, otsa, iso, maxsub, N, F, S, x, T, n0, aN, aF, ax,
     rows = [list(map(float, ln.split())) for ln in out[:G]]
     ax_, aT_, an0 = map(float, out[G].split())
     xf, Tf, nsub = out[G + 1].split()
+    assert out[G + 2].strip() == "1", "the kept-state chemistry adjoint differs from the replay-from-start one"
     aNr = np.array([r[0] for r in rows])
     aFr = np.array([r[1:4] for r in rows])
     aS = np.array([r[4] for r in rows])

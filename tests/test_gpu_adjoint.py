@@ -197,3 +197,29 @@ def test_adjoint_argument_errors():
         rt.step_adjoint(N, F, x, T, n0, e, e.double(), rt.max_dt(), 3, N.clone(), F.clone(), x.clone(),
                         T.clone(), n0.clone(), e.double())
     rt.close()
+
+
+def test_kernel_timing_through_an_adjoint_call():
+    # regression: the tape's forward steps were bracketed twice (an outer
+    # bracket around the step's own per-kernel brackets), which left events
+    # unrecorded and made the profile read fail
+    w = E.make_workload("adjoint64", n=16)
+    G, shape = w["G"], w["shape"]
+    K = 4
+    rt = _rt(shape, G, w["dx"], w["c_red"], K)
+    N0, F0, x0, T0 = to_dev(w["N"]), to_dev(w["F"]), to_dev(w["x"]), to_dev(w["T"])
+    n0 = to_dev(w["n0"])
+    cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
+    gN, gF, gT = torch.zeros_like(N0), torch.zeros_like(F0), torch.zeros_like(T0)
+    gx = torch.ones_like(x0)
+    g_n0, g_rate = torch.zeros_like(n0), torch.zeros_like(rates)
+    rt.profile(True)
+    rt.profile_read()
+    rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+    kern = rt.profile_read()
+    rt.profile(False)
+    rt.close()
+    for kind, launches in (("transport", K - 1), ("chemistry", K - 1), ("adj_forward", K), ("adj_chemistry", K),
+                           ("adj_transport", K), ("adj_sources", 1)):
+        assert kern[kind][0] == launches, (kind, kern[kind])
+        assert kern[kind][1] > 0.0
