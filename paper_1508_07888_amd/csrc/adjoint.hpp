@@ -217,10 +217,11 @@ __host__ __device__ inline void substep_adj(const GroupConsts &gc, const ChemPar
 // Reverse of chem_cell: inputs (N, F, x, T) of the subcycle and dL/d(outputs)
 // -> dL/d(inputs), dL/dn0, dL/dS.  The start state of each substep is
 // recomputed with substep() (identical decisions): from the cell's start when
-// M = 0 (cost quadratic in the cell's substep count K, which is 1 or 2 for
-// almost every cell), else from the nearest of M kept states, one every
-// s = ceil(K / M) substeps (a second forward pass keeps them; about
-// 2K + K s / 2 substeps in all).  Both give the same bits.  With a finite
+// M = 0 (cost quadratic in the cell's substep count K, which is 1 for almost
+// every cell), else from the nearest of M kept states, one every
+// s = ceil(K / M) substeps (kept by the counting pass when K <= M, else by a
+// second forward pass; at most 3K + K s / 2 substeps in all).  Both give the
+// same bits.  With a finite
 // budget the cell gives up when K exceeds it (*deferred = true, outputs
 // meaningless), so a caller can hand long subcycles to the kept-state form.
 template <int G, bool FAST, int M = 0>
@@ -240,10 +241,21 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
     double x = x0, e = e0, rem = p.dt;
     ChemStats st{0, 0, 0, 0};
     int K = 0;
+    // kept start states (M > 0): substeps 0, s, 2s, ...; this pass keeps the
+    // first M (s = 1), a second one is needed only when K > M
+    constexpr int MK = M > 0 ? M : 1;
+    double kN[MK][G], kx[MK], ke[MK], kr[MK];
     while (rem > 0.0) {
         if (K >= budget) {
             *deferred = true;
             return;
+        }
+        if (M > 0 && K < MK) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) kN[K][g] = N[g];
+            kx[K] = x;
+            ke[K] = e;
+            kr[K] = rem;
         }
         const bool last = K >= p.max_substeps;
         double inv[G];
@@ -253,11 +265,8 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
         K++;
         if (last || iso) break;
     }
-    // kept start states (M > 0): substeps 0, s, 2s, ...
-    constexpr int MK = M > 0 ? M : 1;
-    double kN[MK][G], kx[MK], ke[MK], kr[MK];
     const int s = M > 0 ? (K + MK - 1) / MK : 0;
-    if (M > 0 && K > 0) {
+    if (M > 0 && K > MK) {
         double Ns[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) Ns[g] = N0[g];
@@ -346,6 +355,64 @@ __host__ __device__ inline void chem_cell_adj(const GroupConsts &gc, const ChemP
     }
 }
 
+// chem_cell_adj for a subcycle of exactly one substep: the substep that
+// counts it is the one the reverse replays, so its decisions and factors are
+// kept instead of recomputed (same bits as chem_cell_adj).  Returns false,
+// with nothing written, for any other subcycle.
+template <int G, bool FAST>
+__host__ __device__ inline bool chem_cell_adj1(const GroupConsts &gc, const ChemParams &p, const double (&N0)[G],
+                                      const double (&F0)[G][3], double x0, double T0, double n0,
+                                      const double (&S)[G], const double (&aNo)[G], const double (&aFo)[G][3],
+                                      double axo, double aTo, double (&aN)[G], double (&aF)[G][3], double &ax,
+                                      double &aT, double &an0, double (&aS)[G]) {
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    const double eunit = 1.5 * n0 * kKB;
+    const double e0 = eunit * (1.0 + x0) * T0;
+    double N[G], inv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) N[g] = N0[g];
+    double x = x0, e = e0, rem = p.dt;
+    ChemStats st{0, 0, 0, 0};
+    SubInfo info;
+    if (!(rem > 0.0)) return false;
+    if (!substep<G, FAST>(gc, p, 0 >= p.max_substeps, n0, eunit, T0, S, N, x, e, rem, inv, st, &info)) return false;
+    if (rem > 0.0 && !iso && !(0 >= p.max_substeps)) return false;  // a second substep follows
+    double Phi[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        Phi[g] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            aF[g][k] = aFo[g][k] * inv[g];
+            Phi[g] += aFo[g][k] * F0[g][k] * inv[g];
+        }
+        aN[g] = aNo[g];
+        aS[g] = 0.0;
+    }
+    ax = axo;
+    aT = 0.0;
+    an0 = 0.0;
+    double ae = 0.0, arem = 0.0;
+    if (!iso) {
+        const double Tf = e / (eunit * (1.0 + x));
+        ae += aTo / (eunit * (1.0 + x));
+        ax -= aTo * Tf / (1.0 + x);
+        an0 -= aTo * Tf / n0;
+    } else {
+        aT += aTo;
+    }
+    double aFinv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) aFinv[g] = Phi[g] / inv[g];
+    substep_adj<G, FAST>(gc, p, n0, eunit, S, N0, x0, e0, p.dt, info, aFinv, aN, ax, ae, arem, an0, aS, aT);
+    if (!iso) {
+        aT += ae * eunit * (1.0 + x0);
+        ax += ae * eunit * T0;
+        an0 += ae * 1.5 * kKB * (1.0 + x0) * T0;
+    }
+    return true;
+}
+
 // Floor and limiter after the stencil: N* = max(N~, 0); F* = F~ c N*/|F~|
 // when |F~| > c N*.  Forward in place (a = the post values).
 __host__ __device__ __forceinline__ bool floor_limit(double &n, double &fx, double &fy, double &fz, double c, bool &floored) {
@@ -385,16 +452,11 @@ __host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, do
 #ifndef EMMA_ADJ_KEPT
 #define EMMA_ADJ_KEPT 32
 #endif
-// Substeps up to which the first chemistry-adjoint pass recomputes each
-// substep's start from the cell's start (at most budget (budget + 1) / 2
-// substeps); longer subcycles are deferred to the kept-state pass.
-#ifndef EMMA_ADJ_BUDGET
-#define EMMA_ADJ_BUDGET 4
-#endif
 
 // The chemistry adjoint of cell i (and the reverse of the floor and limiter
-// before it).  Returns false, with nothing written, when the cell's subcycle
-// exceeds the budget.
+// before it): M kept states (chem_cell_adj), or M < 0 for the single-substep
+// form (chem_cell_adj1).  Returns false, with nothing written, when the
+// cell's subcycle exceeds the budget (one substep for M < 0).
 template <int G, typename S, bool FAST, int M>
 __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const S *__restrict__ Ft,
                                      const double *__restrict__ xs, const double *__restrict__ Ts,
@@ -423,8 +485,12 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
     double aN[G], aF[G][3], aS[G], ax, aT, an0;
     bool deferred = false;
-    chem_cell_adj<G, FAST, M>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i], aN, aF, ax, aT,
-                              an0, aS, budget, &deferred);
+    if (M < 0)
+        deferred = !chem_cell_adj1<G, FAST>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i], aN,
+                                            aF, ax, aT, an0, aS);
+    else
+        chem_cell_adj<G, FAST, (M < 0 ? 0 : M)>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i],
+                                                aN, aF, ax, aT, an0, aS, budget, &deferred);
     if (deferred) return false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -445,9 +511,12 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     return true;
 }
 
-// First pass, one thread per cell: subcycles of at most EMMA_ADJ_BUDGET
-// substeps; longer ones are appended to the work list (a few wave-long
-// subcycles would otherwise hold their whole wave for their quadratic cost).
+// First pass, one thread per cell: single-substep subcycles (95 % of the
+// cell-steps of the 256^3 benchmark); the others are appended to the work
+// list for the kept-state pass.  Handing the first pass subcycles of up to 2
+// or 4 substeps (replayed from the cell's start) measured slower: 3.7 and
+// 4.3 ms per step at 256^3 against 2.4 ms for this split before the
+// single-substep form.
 template <int G, typename S, bool FAST>
 __global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
                                                   const double *__restrict__ xs, const double *__restrict__ Ts,
@@ -459,8 +528,8 @@ __global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, cons
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool deferred = false;
     if (i < V)
-        deferred = !chem_adj_cell<G, S, FAST, 0>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
-                                                 gU, EMMA_ADJ_BUDGET);
+        deferred = !chem_adj_cell<G, S, FAST, -1>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
+                                                  gU, 1);
     defer_push(wl, deferred, (uint32_t)i);
 }
 

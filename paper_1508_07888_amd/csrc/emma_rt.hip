@@ -710,6 +710,10 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
                 hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
                                    tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
             if (int e = check_launch(c, "k_chem_adj")) return e;
+        }
+        {
+            Timed t(c, KID_ADJ_CHEM_LIST);
+            const WorkList wl{c->work_count, c->work_cells};
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj_list<G, S, true>), dim3(c->list_blocks), dim3(tb), 0, c->stream, Ut,
                                    Ft, tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS,
@@ -778,7 +782,7 @@ extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *
 static const char *kKindNames[KID_COUNT] = {"src_table", "transport", "chemistry", "fused_step",
                                             "diagnostics", "adj_chemistry", "adj_transport",
                                             "adj_sources", "adj_forward", "chemistry_deferred",
-                                            "chemistry_refined"};
+                                            "chemistry_refined", "adj_chemistry_deferred"};
 
 extern "C" int emma_rt_profile_enable(emma_rt_ctx *c, int32_t enable) {
     if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");

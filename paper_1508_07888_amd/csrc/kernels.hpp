@@ -52,6 +52,7 @@ enum KernelKind {
     KID_ADJ_FWD,
     KID_CHEM_LIST,
     KID_CRTA,
+    KID_ADJ_CHEM_LIST,
     KID_COUNT
 };
 

@@ -40,7 +40,7 @@ template <int G> int run() {
         chem_cell_adj<G, false>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, aN, aF, ax, aT, an0, aS);
     for (int g = 0; g < G; ++g) printf("%.17g %.17g %.17g %.17g %.17g\n", aN[g], aF[g][0], aF[g][1], aF[g][2], aS[g]);
     printf("%.17g %.17g %.17g\n", ax, aT, an0);
-    // the kept-state form (3 kept states: several substeps per segment) gives the same bits
+    // the kept-state form gives the same bits: 3 kept states (several substeps per segment) ...
     double bN[G], bF[G][3], bS[G], bx, bT, bn0;
     if (p.otsa && !p.isothermal)
         chem_cell_adj<G, true, 3>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
@@ -48,6 +48,13 @@ template <int G> int run() {
         chem_cell_adj<G, false, 3>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
     bool same = memcmp(&ax, &bx, 8) == 0 && memcmp(&aT, &bT, 8) == 0 && memcmp(&an0, &bn0, 8) == 0 &&
                 memcmp(aN, bN, sizeof aN) == 0 && memcmp(aF, bF, sizeof aF) == 0 && memcmp(aS, bS, sizeof aS) == 0;
+    // and with 64 kept states (every start state kept by the counting pass when K <= 64)
+    if (p.otsa && !p.isothermal)
+        chem_cell_adj<G, true, 64>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
+    else
+        chem_cell_adj<G, false, 64>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
+    same = same && memcmp(&ax, &bx, 8) == 0 && memcmp(&aT, &bT, 8) == 0 && memcmp(&an0, &bn0, 8) == 0 &&
+           memcmp(aN, bN, sizeof aN) == 0 && memcmp(aF, bF, sizeof aF) == 0 && memcmp(aS, bS, sizeof aS) == 0;
     // forward value for a consistency check
     double N[G], F[G][3]; for (int g = 0; g < G; ++g) { N[g] = Nin[g]; for (int k = 0; k < 3; ++k) F[g][k] = Fin[g][k]; }
     double xx = x, TT = T;
@@ -55,6 +62,13 @@ template <int G> int run() {
                                              : chem_cell<G, false>(gc, p, N, F, xx, TT, n0, S);
     printf("%.17g %.17g %d\n", xx, TT, st.substeps);
     printf("%d\n", same ? 1 : 0);
+    // the single-substep form: taken exactly for one-substep subcycles, same bits
+    bool one = (p.otsa && !p.isothermal)
+                   ? chem_cell_adj1<G, true>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS)
+                   : chem_cell_adj1<G, false>(gc, p, Nin, Fin, x, T, n0, S, aNo, aFo, axo, aTo, bN, bF, bx, bT, bn0, bS);
+    bool same1 = one && memcmp(&ax, &bx, 8) == 0 && memcmp(&aT, &bT, 8) == 0 && memcmp(&an0, &bn0, 8) == 0 &&
+                 memcmp(aN, bN, sizeof aN) == 0 && memcmp(aF, bF, sizeof aF) == 0 && memcmp(aS, bS, sizeof aS) == 0;
+    printf("%d %d\n", one ? 1 : 0, same1 ? 1 : 0);
     return 0;
 }
 int main() { int G; scanf("%d", &G); if (G == 1) return run<1>(); if (G == 2) return run<2>(); return run<3>(); }
@@ -109,6 +123,9 @@ def _run_adj(exe, G, g, c, dt, otsa, iso, maxsub, N, F, S, x, T, n0, aN, aF, ax,
     ax_, aT_, an0 = map(float, out[G].split())
     xf, Tf, nsub = out[G + 1].split()
     assert out[G + 2].strip() == "1", "the kept-state chemistry adjoint differs from the replay-from-start one"
+    one, same1 = map(int, out[G + 3].split())
+    assert one == (int(nsub) == 1), "the single-substep form must be taken exactly for one-substep subcycles"
+    assert same1 == one, "the single-substep chemistry adjoint differs from the general one"
     aNr = np.array([r[0] for r in rows])
     aFr = np.array([r[1:4] for r in rows])
     aS = np.array([r[4] for r in rows])
@@ -253,3 +270,20 @@ def test_closure_jacobian_matches_oracle_pressure_differences():
             step = h * Fn
             num_F = (oracle.pressure(N, F + step * e, c) - oracle.pressure(N, F - step * e, c)) / (2 * step)
             assert np.allclose(dPdF, num_F, rtol=1e-5, atol=1e-6 * N / Fn)
+
+
+@pytest.mark.parametrize("G,Nval,T,x,otsa", [(3, 0.0, 100.0, 1.2e-3, 1), (3, 1e-9, 100.0, 1.2e-3, 1),
+                                             (2, 1e-10, 300.0, 1e-2, 1), (1, 1e-9, 100.0, 1.2e-3, 0)])
+def test_single_substep_form_of_the_chemistry_adjoint(prog, G, Nval, T, x, otsa):
+    # the common case of the benchmark (a dark or faintly lit, cold, neutral
+    # cell: one substep covers dt); _run_adj checks that the single-substep
+    # form is taken and gives the general form's bits
+    g = oracle.group_constants(E.T_BB, E.EDGES[G])
+    c = 0.1 * E.C_LIGHT
+    N = np.full(G, Nval)
+    F = np.zeros((G, 3))
+    F[:, 0] = 0.3 * c * N
+    rng = np.random.default_rng(G)
+    out = _run_adj(prog, G, g, c, 7e9, otsa, 0, 100000, N, F, np.zeros(G), x, T, 1e-3,
+                   rng.standard_normal(G), rng.standard_normal((G, 3)), 1.0, 1e-3)
+    assert out[-1] == 1

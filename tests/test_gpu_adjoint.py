@@ -220,6 +220,6 @@ def test_kernel_timing_through_an_adjoint_call():
     rt.profile(False)
     rt.close()
     for kind, launches in (("transport", K - 1), ("chemistry", K - 1), ("adj_forward", K), ("adj_chemistry", K),
-                           ("adj_transport", K), ("adj_sources", 1)):
+                           ("adj_chemistry_deferred", K), ("adj_transport", K), ("adj_sources", 1)):
         assert kern[kind][0] == launches, (kind, kern[kind])
         assert kern[kind][1] > 0.0
