@@ -166,7 +166,35 @@ def summarize_sq(sq_dir, out_path, command):
                      f"{m.get('SQ_WAVE_CYCLES', 0) / w:.0f} |")
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    # machine-readable means per kernel, for the benchmark's VALU figures
+    side = {"source_hash": source_hash(), "command": command,
+            "kernels": {name: {c: sum(v) / len(v) for c, v in d.items()} for name, d in agg.items()}}
+    with open(os.path.splitext(out_path)[0] + ".json", "w") as fh:
+        json.dump(side, fh, indent=1)
     return out_path
+
+
+def valu_from_profiles(kernel_prefix):
+    """Per-wave VALU figures of one kernel instantiation from the committed SQ
+    counter summary of the split path: instructions, VALU-active and
+    resident cycles, and the share of a SIMD's issue slots its resident
+    waves use (waves per SIMD x active / resident); None when there is no
+    summary or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "split_step_throughput256_sq_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    for name, m in d["kernels"].items():
+        if name.startswith(kernel_prefix):
+            w = max(m.get("SQ_WAVES", 0.0), 1.0)
+            act, cyc = m["SQ_ACTIVE_INST_VALU"] / w, m["SQ_WAVE_CYCLES"] / w
+            return {"kernel": name, "valu_instr_per_wave": m["SQ_INSTS_VALU"] / w,
+                    "valu_active_per_wave": act, "wave_cycles": cyc, "waves_per_simd": 4,
+                    "simd_valu_busy": 4 * act / cyc}
+    return None
 
 
 def summarize_trace(trace_dir, out_path, command):
@@ -515,6 +543,8 @@ def main():
                    "sources": int(w["src_cell"].size), "c_red_over_c": w["c_red"] / E.C_LIGHT,
                    "precision": "mixed", "path": args.path},
         "roofline": roofline,
+        # what binds the dominant kernel besides HBM: its VALU issue (SQ counters)
+        "chemistry_valu": valu_from_profiles("void emma::k_chem<3, float, false, true>"),
         "group_cell_updates_per_s": mixed["value"] * G,
         "kernels_ms": {k: v[1] / v[0] for k, v in kern.items()},
         "substeps_per_cell_step": mixed["diag"]["substeps"] / (mixed["V"] * args.steps),
