@@ -9,8 +9,9 @@
 //                    own substep() (identical decisions), then runs them
 //                    backwards; also reverses the floor and limiter.  Adds
 //                    dL/dn0 and dL/dS (per source cell).
-//   k_transport_adj  per cell, gather form (no atomics): the transpose of the
-//                    radius-1 stencil with the closure Jacobian dP/d(N, F).
+//   k_transport_adj  gather form (no atomics), z-marching columns: the
+//                    transpose of the radius-1 stencil with the closure
+//                    Jacobian dP/d(N, F).
 //   k_src_grad       dL/d(source rate) = sum_g frac_g / dx^3 dL/dS_g(host cell).
 #pragma once
 
@@ -611,74 +612,119 @@ __host__ __device__ __forceinline__ void flux_jac_t(const ClosureJac &J, int d, 
     }
 }
 
-// Transpose of the transport step.  U_i enters U*_{i+e_d} through A_d(U_i)
-// and U*_{i-e_d} through B_d(U_i) (A = (Ft + c U)/2, B = (c U - Ft)/2), and
-// U*_i through -c U_i per axis; at a non-periodic face, cell i also sees the
-// ghost of itself (A_d(ghost) across its minus face, B_d(ghost) across its
-// plus face): ghost = U_i (transmissive), U_i with F_d reversed (reflective,
-// a symmetric map R, so the term is R A'(R U)^T g_i) or a constant (inflow).
-template <int G, typename S>
+// Transpose of the transport step at one cell and group.  U_i enters
+// U*_{i+e_d} through A_d(U_i) and U*_{i-e_d} through B_d(U_i)
+// (A = (Ft + c U)/2, B = (c U - Ft)/2), and U*_i through -c U_i per axis; at a
+// non-periodic face, cell i also sees the ghost of itself (A_d(ghost) across
+// its minus face, B_d(ghost) across its plus face): ghost = U_i
+// (transmissive), U_i with F_d reversed (reflective, a symmetric map R, so
+// the term is R A'(R U)^T g_i) or a constant (inflow).  gi = dL/dU*_i,
+// vnb[d][s] = dL/dU* of the neighbour across face (d, s) (zero across a
+// non-periodic face).
+template <typename S>
+__device__ __forceinline__ void transport_adj_cell(double n, const double (&Fv)[3], const double (&gi)[4],
+                                                   const double (&vnb)[3][2][4], const Nbrs &nb, double c,
+                                                   double lam, const Bounds<S> &bnd, double (&out)[4]) {
+    const double hl = 0.5 * lam;
+    const ClosureJac J = closure_jac(n, Fv[0], Fv[1], Fv[2], c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = (1.0 - 3.0 * c * lam) * gi[q];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // ordinary neighbours: (lam/2) [c (v+ + v-) + M_d(U)^T (v+ - v-)]
+        double dv[4], m[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dv[q] = vnb[d][1][q] - vnb[d][0][q];
+        flux_jac_t(J, d, c, dv, m);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] += hl * (c * (vnb[d][1][q] + vnb[d][0][q]) + m[q]);
+        // ghosts of this cell across its own non-periodic faces
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int face = nb.face[d][s];
+            if (face < 0 || bnd.kind[face] == BC_INFLOW) continue;
+            const bool refl = bnd.kind[face] == BC_REFLECTIVE;
+            double Fg[3] = {Fv[0], Fv[1], Fv[2]};
+            if (refl) Fg[d] = -Fg[d];
+            const ClosureJac Jg = closure_jac(n, Fg[0], Fg[1], Fg[2], c);
+            double mg[4];
+            flux_jac_t(Jg, d, c, gi, mg);
+            const double sg = s ? -1.0 : 1.0;  // A across the minus face, B across the plus face
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double t = hl * (c * gi[q] + sg * mg[q]);
+                if (refl && q == 1 + d) t = -t;
+                out[q] += t;
+            }
+        }
+    }
+}
+
+// Planes of a z chunk of the transport adjoint.
+constexpr int kAdjLZ = 16;
+
+// Gather form of the transport transpose for one group (blockIdx.y): blocks
+// of 64 x 4 columns march up kAdjLZ-plane z chunks, keeping dL/dU* of the
+// planes below, at and above the cell in registers, so the z neighbours are
+// read from HBM once (cell-parallel, every cell read its six neighbours
+// from memory: three times the algorithmic bytes); x and y neighbours come
+// through the caches.  Blocks are renumbered per XCD like the forward tiles.
+template <typename S>
 __global__ __launch_bounds__(256) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
                                                        const double *__restrict__ gU, S *__restrict__ gN,
                                                        S *__restrict__ gF, Grid gr, double c, double lam,
                                                        Bounds<S> bnd) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= gr.V) return;
+    const int g = blockIdx.y;
     const int64_t V = gr.V;
-    const int x = (int)(i % gr.nx);
-    const int y = (int)((i / gr.nx) % gr.ny);
-    const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
-    const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
-    const double hl = 0.5 * lam;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const double n = (double)N[(int64_t)g * V + i];
-        const double Fv[3] = {(double)F[((int64_t)g * 3) * V + i], (double)F[((int64_t)g * 3 + 1) * V + i],
-                              (double)F[((int64_t)g * 3 + 2) * V + i]};
-        const ClosureJac J = closure_jac(n, Fv[0], Fv[1], Fv[2], c);
-        const double *gUg = gU + (int64_t)(4 * g) * V;
-        double gi[4], out[4];
+    const int ntx = (gr.nx + 63) / 64, nty = (gr.ny + 3) / 4;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int x = (t % ntx) * 64 + (int)(threadIdx.x & 63);
+    const int y = ((t / ntx) % nty) * 4 + (int)(threadIdx.x >> 6);
+    const int z0 = (t / (ntx * nty)) * kAdjLZ;
+    if (x >= gr.nx || y >= gr.ny || z0 >= gr.nz) return;  // no barriers below
+    const int z1 = min(z0 + kAdjLZ, gr.nz);
+    const int64_t plane = (int64_t)gr.nx * gr.ny;
+    const double *gUg = gU + (int64_t)(4 * g) * V;
+    const S *Ng = N + (int64_t)g * V;
+    const S *Fg = F + (int64_t)(3 * g) * V;
+    S *gNg = gN + (int64_t)g * V;
+    S *gFg = gF + (int64_t)(3 * g) * V;
+    int64_t i = (int64_t)z0 * plane + (int64_t)y * gr.nx + x;
+    double below[4], here[4], above[4];
+    {
+        const Nbrs nb = neighbours(gr, bnd, i, x, y, z0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            gi[q] = gUg[(int64_t)q * V + i];
-            out[q] = (1.0 - 3.0 * c * lam) * gi[q];
+            below[q] = nb.face[2][0] < 0 ? gUg[(int64_t)q * V + nb.idx[2][0]] : 0.0;
+            here[q] = gUg[(int64_t)q * V + i];
         }
+    }
+    for (int z = z0; z < z1; ++z, i += plane) {
+        const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
+        double vnb[3][2][4];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            // ordinary neighbours: (lam/2) [c (v+ + v-) + M_d(U)^T (v+ - v-)]
-            double vp[4], vm[4], dv[4], m[4];
+        for (int q = 0; q < 4; ++q) {
+            above[q] = nb.face[2][1] < 0 ? gUg[(int64_t)q * V + nb.idx[2][1]] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                vp[q] = nb.face[d][1] < 0 ? gUg[(int64_t)q * V + nb.idx[d][1]] : 0.0;
-                vm[q] = nb.face[d][0] < 0 ? gUg[(int64_t)q * V + nb.idx[d][0]] : 0.0;
-                dv[q] = vp[q] - vm[q];
-            }
-            flux_jac_t(J, d, c, dv, m);
+            for (int d = 0; d < 2; ++d)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) out[q] += hl * (c * (vp[q] + vm[q]) + m[q]);
-            // ghosts of this cell across its own non-periodic faces
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int face = nb.face[d][s];
-                if (face < 0 || bnd.kind[face] == BC_INFLOW) continue;
-                const bool refl = bnd.kind[face] == BC_REFLECTIVE;
-                double Fg[3] = {Fv[0], Fv[1], Fv[2]};
-                if (refl) Fg[d] = -Fg[d];
-                const ClosureJac Jg = closure_jac(n, Fg[0], Fg[1], Fg[2], c);
-                double mg[4];
-                flux_jac_t(Jg, d, c, gi, mg);
-                const double sg = s ? -1.0 : 1.0;  // A across the minus face, B across the plus face
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    double t = hl * (c * gi[q] + sg * mg[q]);
-                    if (refl && q == 1 + d) t = -t;
-                    out[q] += t;
-                }
-            }
+                for (int s = 0; s < 2; ++s)
+                    vnb[d][s][q] = nb.face[d][s] < 0 ? gUg[(int64_t)q * V + nb.idx[d][s]] : 0.0;
+            vnb[2][0][q] = below[q];
+            vnb[2][1][q] = above[q];
         }
-        gN[(int64_t)g * V + i] = (S)out[0];
+        const double n = (double)Ng[i];
+        const double Fv[3] = {(double)Fg[i], (double)Fg[V + i], (double)Fg[2 * V + i]};
+        double out[4];
+        transport_adj_cell<S>(n, Fv, here, vnb, nb, c, lam, bnd, out);
+        gNg[i] = (S)out[0];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gF[((int64_t)g * 3 + k) * V + i] = (S)out[1 + k];
+        for (int k = 0; k < 3; ++k) gFg[(int64_t)k * V + i] = (S)out[1 + k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            below[q] = here[q];
+            here[q] = above[q];
+        }
     }
 }
 

@@ -726,7 +726,9 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
         if (int e = check_launch(c, "k_chem_adj_list")) return e;
         {
             Timed t(c, KID_ADJ_TRANSPORT);
-            hipLaunchKernelGGL((k_transport_adj<G, S>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
+            const unsigned tiles = (unsigned)(((gr.nx + 63) / 64) * ((gr.ny + 3) / 4) *
+                                              ((gr.nz + kAdjLZ - 1) / kAdjLZ));
+            hipLaunchKernelGGL((k_transport_adj<S>), dim3(tiles, G), dim3(tb), 0, c->stream, tN(s), tF(s),
                                c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport_adj")) return e;

@@ -63,14 +63,6 @@ template <typename R> struct TileArgs {
     Bounds<R> bnd;
 };
 
-// Physical tile of block b when the hardware deals blocks to 8 XCDs
-// round-robin: XCD k gets the logical range [k*q + min(k, r), ...).
-__device__ inline int xcd_tile(int b, int nb) {
-    const int q = nb >> 3, r = nb & 7;
-    const int k = b & 7, i = b >> 3;
-    return k * q + (k < r ? k : r) + i;
-}
-
 template <typename R> struct alignas(4 * sizeof(R) > 16 ? 16 : 4 * sizeof(R)) Vec4 {
     R n, fx, fy, fz;
 };

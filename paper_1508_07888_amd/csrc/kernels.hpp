@@ -67,6 +67,14 @@ __device__ inline int wave_max(int v) {
     return v;
 }
 
+// Physical tile of block b when the hardware deals blocks to 8 XCDs
+// round-robin: XCD k gets the logical range [k*q + min(k, r), ...).
+__device__ inline int xcd_tile(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int k = b & 7, i = b >> 3;
+    return k * q + (k < r ? k : r) + i;
+}
+
 // Counters live in kCntSlots copies so that concurrent waves do not all hit
 // one address; slot = block index mod kCntSlots, summed on the host.
 constexpr int kCntSlots = 64;
