@@ -570,24 +570,29 @@ struct ClosureJac {
 __host__ __device__ __forceinline__ ClosureJac closure_jac(double N, double Fx, double Fy, double Fz, double c) {
     ClosureJac j{1.0 / 3.0, 0.0, 0.0, 0.0, 0.0, {0.0, 0.0, 0.0}};
     if (!(N > 0.0)) return j;  // P = N/3 I: only dP/dN = I/3
-    const double icn = 1.0 / (c * N);
+    // reciprocals to about 1 ulp (recip_fp64) rather than correctly rounded
+    // divisions: these factors only scale gradients
+    const double icn = recip_fp64(c * N);
     j.g[0] = Fx * icn;
     j.g[1] = Fy * icn;
     j.g[2] = Fz * icn;
     const double q = j.g[0] * j.g[0] + j.g[1] * j.g[1] + j.g[2] * j.g[2];
     if (q >= 1.0) {
+        const double rq = recip_fp64(q);
         j.aN = 0.0;
-        j.K = 1.0 / q;
-        j.KN = 1.0 / q;
-        j.GB = -2.0 / (q * q);
+        j.K = rq;
+        j.KN = rq;
+        j.GB = -2.0 * rq * rq;
         return j;
     }
     const double s = sqrt(4.0 - 3.0 * q);
     const double den = 5.0 + 2.0 * s, t = 2.0 + s;
-    const double h = (6.0 + 3.0 / t) / den;
-    const double hp = (1.5 / s) * (3.0 / (t * t * den) + 2.0 * (6.0 + 3.0 / t) / (den * den));
-    const double chi = (1.0 + 2.0 * q * h) / 3.0;
-    const double dchi = 2.0 * (h + q * hp) / 3.0;
+    const double rt = recip_fp64(t), rs = recip_fp64(s), rden = recip_fp64(den);
+    const double u = 6.0 + 3.0 * rt;
+    const double h = u * rden;
+    const double hp = (1.5 * rs) * (3.0 * rt * rt * rden + 2.0 * u * rden * rden);
+    const double chi = (1.0 + 2.0 * q * h) * (1.0 / 3.0);
+    const double dchi = 2.0 * (h + q * hp) * (1.0 / 3.0);
     j.aN = 0.5 * (1.0 - chi) + dchi * q;
     j.GA = -dchi;
     j.K = h;
