@@ -105,8 +105,8 @@ typedef struct {
     /* Faces in the order x-, x+, y-, y+, z-, z+; emma_rt_bc values, 0 (periodic)
        by default.  Both faces of an axis are periodic or neither. */
     int32_t bc[6];
-    int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL needs
-                                   path = EMMA_RT_PATH_REFERENCE and no adjoint */
+    int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL runs on the split
+                                   and reference paths (not fused), without adjoint */
     int32_t reserved;           /* 0 */
     double inflow[6];           /* photons cm^-2 s^-1 through each INFLOW face, >= 0 */
 } emma_rt_config;

@@ -159,8 +159,8 @@ static const char *config_error(const emma_rt_config *cfg) {
     for (int f = 0; f < 6; ++f)
         if (!(cfg->inflow[f] >= 0) || !isfinite(cfg->inflow[f])) return "inflow must be finite and >= 0";
     if (cfg->flux != EMMA_RT_FLUX_GLF && cfg->flux != EMMA_RT_FLUX_HLL) return "bad flux";
-    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->path != EMMA_RT_PATH_REFERENCE)
-        return "the HLL flux runs on the reference path only (path = EMMA_RT_PATH_REFERENCE)";
+    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->path == EMMA_RT_PATH_FUSED)
+        return "the HLL flux runs on the split and reference paths (not EMMA_RT_PATH_FUSED)";
     if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->adjoint_max_steps > 0)
         return "the adjoint differentiates the GLF flux only (adjoint_max_steps must be 0 with HLL)";
     if (cfg->path != EMMA_RT_PATH_REFERENCE &&
@@ -386,7 +386,11 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
         return EMMA_RT_OK;
     }
     for (int s = 0; s < n_steps; ++s) {
-        if (c->cfg.path == EMMA_RT_PATH_SPLIT) {
+        if (c->cfg.path == EMMA_RT_PATH_SPLIT && c->cfg.flux == EMMA_RT_FLUX_HLL) {
+            Timed t(c, KID_TRANSPORT);
+            launch_transport_tiled_hll<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
+                                                   bounds_of<S>(c));
+        } else if (c->cfg.path == EMMA_RT_PATH_SPLIT) {
             Timed t(c, KID_TRANSPORT);
             launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
                                                bounds_of<S>(c));
@@ -536,7 +540,10 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
     for (int s = 0; s < n_steps; ++s) {
         {
             Timed t(c, KID_TRANSPORT);
-            if (c->cfg.path != EMMA_RT_PATH_REFERENCE)
+            if (c->cfg.path != EMMA_RT_PATH_REFERENCE && c->cfg.flux == EMMA_RT_FLUX_HLL)
+                launch_transport_tiled_hll<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
+                                                       bounds_of<S>(c));
+            else if (c->cfg.path != EMMA_RT_PATH_REFERENCE)
                 launch_transport_tiled<G, S, DIAG>(c->stream, N, F, Ns, Fs, gr, cp, dt / c->cfg.dx, c->cnt,
                                                    bounds_of<S>(c));
             else if (c->cfg.flux == EMMA_RT_FLUX_HLL)

@@ -126,6 +126,251 @@ __device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R P[6], R c) {
     return Vec4<R>{c * u.n - u.fz, c * u.fx - c * c * P[2], c * u.fy - c * c * P[4], c * u.fz - c * c * P[5]};
 }
 
+// ------------------------------------------------------------ HLL, tiled
+// The HLL flux with M1 wave speeds (reference path: kernels.hpp k_transport)
+// does not split into per-cell parts: a face needs both sides' state U, flux
+// Ft_d = (F_d, c^2 P_xd, c^2 P_yd, c^2 P_zd) and speeds.  Each cell computes
+// its closure and its speeds along the three axes once (in double, as the
+// reference path does), publishes (U, Ft_x, Ft_y, speeds) in LDS for its x/y
+// neighbours, keeps the z side in registers, and evaluates its own faces.
+template <typename R> struct Speeds2 {
+    R lo, hi;  // min(0, lambda-), max(0, lambda+) along one axis
+};
+
+template <typename R>
+__device__ __forceinline__ Speeds2<R> hll_speeds(const Vec4<R> &u, int d, R c) {
+    const R fd = d == 0 ? u.fx : (d == 1 ? u.fy : u.fz);
+    double lmn, lmx;
+    m1_speeds<double>((double)u.n, (double)fd, (double)c, lmn, lmx);
+    return Speeds2<R>{(R)(lmn < 0.0 ? lmn : 0.0), (R)(lmx > 0.0 ? lmx : 0.0)};
+}
+
+template <typename R>
+__device__ __forceinline__ Vec4<R> hll_ft(const Vec4<R> &u, const R P[6], R c, int d) {
+#pragma clang fp contract(off)
+    const R cc = c * c;
+    const int i0 = d == 0 ? 0 : (d == 1 ? 1 : 2), i1 = d == 0 ? 1 : (d == 1 ? 3 : 4),
+              i2 = d == 0 ? 2 : (d == 1 ? 4 : 5);
+    return Vec4<R>{d == 0 ? u.fx : (d == 1 ? u.fy : u.fz), cc * P[i0], cc * P[i1], cc * P[i2]};
+}
+
+// (a+ Ft(L) - a- Ft(R) + a+ a- (U_R - U_L)) / (a+ - a-)
+template <typename R>
+__device__ __forceinline__ Vec4<R> hll_face(const Vec4<R> &uL, const Vec4<R> &fL, Speeds2<R> sL, const Vec4<R> &uR,
+                                            const Vec4<R> &fR, Speeds2<R> sR) {
+#pragma clang fp contract(off)
+    const R am = sL.lo < sR.lo ? sL.lo : sR.lo;
+    const R ap = sL.hi > sR.hi ? sL.hi : sR.hi;
+    const R inv = FastMath<R>::rcp(ap - am), pm = ap * am;
+    return Vec4<R>{(ap * fL.n - am * fR.n + pm * (uR.n - uL.n)) * inv,
+                   (ap * fL.fx - am * fR.fx + pm * (uR.fx - uL.fx)) * inv,
+                   (ap * fL.fy - am * fR.fy + pm * (uR.fy - uL.fy)) * inv,
+                   (ap * fL.fz - am * fR.fz + pm * (uR.fz - uL.fz)) * inv};
+}
+
+// Split-path transport with the HLL flux, one group per launch (group 0 of
+// the arguments), blocks of 64 x TY columns marching up LZ-plane z chunks.
+// Halo roles, ghosts and the z window follow k_tiled; LDS holds, per plane
+// (double-buffered), U of the tile and its x/y halo, Ft_x and the x speeds of
+// the tile and its x halo, Ft_y and the y speeds of the tile and its y halo.
+template <typename R, bool DIAG, int TY, bool FULL>
+__global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
+    __shared__ Vec4<R> lU[2][TY + 2][kTX + 2];
+    __shared__ Vec4<R> lFx[2][TY][kTX + 2];
+    __shared__ Speeds2<R> lSx[2][TY][kTX + 2];
+    __shared__ Vec4<R> lFy[2][TY + 2][kTX];
+    __shared__ Speeds2<R> lSy[2][TY + 2][kTX];
+    const int tid = threadIdx.x;
+    const int tx = tid & (kTX - 1), ty = tid >> 6;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile_x = t % a.ntx, tile_y = (t / a.ntx) % a.nty, tile_z = t / (a.ntx * a.nty);
+    const int nx = a.gr.nx, ny = a.gr.ny, nz = a.gr.nz;
+    const int64_t V = a.gr.V;
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const int x0 = tile_x * kTX, y0 = tile_y * TY, z0 = tile_z * a.LZ;
+    const int z1 = min(z0 + a.LZ, nz);
+    const int w = min(kTX, nx - x0), h = min(TY, ny - y0);
+    const bool active = FULL || (tx < w && ty < h);
+    const uint32_t col = active ? (uint32_t)(y0 + ty) * nx + (x0 + tx) : 0u;
+    constexpr uint32_t E = sizeof(R);
+    const Bounds<R> &bd = a.bnd;
+    // halo role as in k_tiled: 0 row below, 1 row above, 2 column left, 3 column right
+    int hrole = -1, hlx = 0, hly = 0, hface = -1;
+    uint32_t hcol = 0;
+    if (tid < kTX) {
+        if (tid < w) {
+            hrole = 0; hlx = tid + 1; hly = 0;
+            int yy = y0 - 1;
+            if (yy < 0) {
+                if (bd.kind[2] == BC_PERIODIC) yy = ny - 1;
+                else { yy = 0; hface = 2; }
+            }
+            hcol = (uint32_t)yy * nx + x0 + tid;
+        }
+    } else if (tid < 2 * kTX) {
+        const int cx = tid - kTX;
+        if (cx < w) {
+            hrole = 1; hlx = cx + 1; hly = h + 1;
+            int yy = y0 + h;
+            if (yy >= ny) {
+                if (bd.kind[3] == BC_PERIODIC) yy = 0;
+                else { yy = ny - 1; hface = 3; }
+            }
+            hcol = (uint32_t)yy * nx + x0 + cx;
+        }
+    } else if (tid < 2 * kTX + TY) {
+        const int cy = tid - 2 * kTX;
+        if (cy < h) {
+            hrole = 2; hlx = 0; hly = cy + 1;
+            int xx = x0 - 1;
+            if (xx < 0) {
+                if (bd.kind[0] == BC_PERIODIC) xx = nx - 1;
+                else { xx = 0; hface = 0; }
+            }
+            hcol = (uint32_t)(y0 + cy) * nx + xx;
+        }
+    } else if (tid < 2 * kTX + 2 * TY) {
+        const int cy = tid - 2 * kTX - TY;
+        if (cy < h) {
+            hrole = 3; hlx = w + 1; hly = cy + 1;
+            int xx = x0 + w;
+            if (xx >= nx) {
+                if (bd.kind[1] == BC_PERIODIC) xx = 0;
+                else { xx = nx - 1; hface = 1; }
+            }
+            hcol = (uint32_t)(y0 + cy) * nx + xx;
+        }
+    }
+    const bool zlo_ghost = bd.kind[4] != BC_PERIODIC, zhi_ghost = bd.kind[5] != BC_PERIODIC;
+    int hkind = BC_PERIODIC, hd = 0;
+    R hsgn = R(1), hphi = R(0);
+    if (hface >= 0) {
+        hkind = bd.kind[hface];
+        hd = hface >> 1;
+        hsgn = (hface & 1) ? R(-1) : R(1);
+        hphi = bd.phi[hface][0];
+    }
+    const uint32_t hsrc = hrole >= 0 ? hcol : col;
+    const R c = a.c;
+    auto zwrap = [nz](int z) { return (uint32_t)((z % nz + nz) % nz); };
+    auto load1 = [&](uint32_t off) {
+        Vec4<R> u[1];
+        load_cell<1>(a.N, a.F, V, off * E, u);
+        return u[0];
+    };
+    // z window: planes z (cur) and z + 1 (nxt) with their closures, the z
+    // side (Ft_z, speeds) of both, and the flux through the face below z
+    Vec4<R> cur = load1(zwrap(z0) * plane + col);
+    Vec4<R> nxt = load1(zwrap(min(z0 + 1, z1)) * plane + col);
+    Vec4<R> um = load1(zwrap(z0 - 1) * plane + col);
+    if (z0 == 0 && zlo_ghost) um = ghost4(bd, 4, 0, c, cur);
+    if (z0 + 1 == nz && zhi_ghost) nxt = ghost4(bd, 5, 0, c, cur);
+    R Pc[6], Pn[6];
+    Vec4<R> flo;
+    {
+        R Pm[6];
+        m1_pressure(um.n, um.fx, um.fy, um.fz, c, Pm);
+        m1_pressure(cur.n, cur.fx, cur.fy, cur.fz, c, Pc);
+        flo = hll_face(um, hll_ft(um, Pm, c, 2), hll_speeds(um, 2, c), cur, hll_ft(cur, Pc, c, 2),
+                       hll_speeds(cur, 2, c));
+    }
+    m1_pressure(nxt.n, nxt.fx, nxt.fy, nxt.fz, c, Pn);
+    Vec4<R> hal = load1((uint32_t)z0 * plane + hsrc);
+    int64_t nlim = 0, nneg = 0;
+    int buf = 0;
+    for (int z = z0; z < z1; ++z) {
+        const uint32_t zc = (uint32_t)z * plane + col;
+        // loads for the next plane fly during this one
+        Vec4<R> nn = load1(zwrap(min(z + 2, z1)) * plane + col);
+        const Vec4<R> hal_next = load1((uint32_t)min(z + 1, z1 - 1) * plane + hsrc);
+        // publish plane z: own cell
+        const Vec4<R> ftx = hll_ft(cur, Pc, c, 0), fty = hll_ft(cur, Pc, c, 1);
+        const Speeds2<R> sx = hll_speeds(cur, 0, c), sy = hll_speeds(cur, 1, c);
+        if (active) {
+            lU[buf][ty + 1][tx + 1] = cur;
+            lFx[buf][ty][tx + 1] = ftx;
+            lSx[buf][ty][tx + 1] = sx;
+            lFy[buf][ty + 1][tx] = fty;
+            lSy[buf][ty + 1][tx] = sy;
+        }
+        // halo cell (the ghost across a non-periodic face)
+        if (hrole >= 0) {
+            Vec4<R> hv = hal;
+            if (hkind == BC_REFLECTIVE) {
+                if (hd == 0) hv.fx = -hv.fx;
+                else hv.fy = -hv.fy;
+            } else if (hkind == BC_INFLOW) {
+                hv.n = hphi / c;
+                hv.fx = hd == 0 ? hsgn * hphi : R(0);
+                hv.fy = hd == 1 ? hsgn * hphi : R(0);
+                hv.fz = R(0);
+            }
+            R Ph[6];
+            m1_pressure(hv.n, hv.fx, hv.fy, hv.fz, c, Ph);
+            lU[buf][hly][hlx] = hv;
+            if (hrole <= 1) {  // row below / above: y side
+                lFy[buf][hly][hlx - 1] = hll_ft(hv, Ph, c, 1);
+                lSy[buf][hly][hlx - 1] = hll_speeds(hv, 1, c);
+            } else {           // column left / right: x side
+                lFx[buf][hly - 1][hlx] = hll_ft(hv, Ph, c, 0);
+                lSx[buf][hly - 1][hlx] = hll_speeds(hv, 0, c);
+            }
+        }
+        // z side of plane z + 1 and the face above z
+        R Pnn[6];
+        const Vec4<R> fup = hll_face(cur, hll_ft(cur, Pc, c, 2), hll_speeds(cur, 2, c), nxt, hll_ft(nxt, Pn, c, 2),
+                                     hll_speeds(nxt, 2, c));
+        __syncthreads();
+        Vec4<R> us;
+        {
+#pragma clang fp contract(off)
+            const Vec4<R> fxl = hll_face(lU[buf][ty + 1][tx], lFx[buf][ty][tx], lSx[buf][ty][tx], cur, ftx, sx);
+            const Vec4<R> fxr =
+                hll_face(cur, ftx, sx, lU[buf][ty + 1][tx + 2], lFx[buf][ty][tx + 2], lSx[buf][ty][tx + 2]);
+            const Vec4<R> fyl = hll_face(lU[buf][ty][tx + 1], lFy[buf][ty][tx], lSy[buf][ty][tx], cur, fty, sy);
+            const Vec4<R> fyr =
+                hll_face(cur, fty, sy, lU[buf][ty + 2][tx + 1], lFy[buf][ty + 2][tx], lSy[buf][ty + 2][tx]);
+            const R lam = a.lam;
+            R n = cur.n + lam * ((fxl.n - fxr.n) + (fyl.n - fyr.n) + (flo.n - fup.n));
+            R fx = cur.fx + lam * ((fxl.fx - fxr.fx) + (fyl.fx - fyr.fx) + (flo.fx - fup.fx));
+            R fy = cur.fy + lam * ((fxl.fy - fxr.fy) + (fyl.fy - fyr.fy) + (flo.fy - fup.fy));
+            R fz = cur.fz + lam * ((fxl.fz - fxr.fz) + (fyl.fz - fyr.fz) + (flo.fz - fup.fz));
+            if (n < R(0)) { n = R(0); if (active) nneg++; }
+            const R F2 = fx * fx + fy * fy + fz * fz;
+            const R cn = c * n;
+            if (F2 > cn * cn) {
+                const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
+                fx *= sc; fy *= sc; fz *= sc;
+                if (active) nlim++;
+            }
+            us = Vec4<R>{n, fx, fy, fz};
+        }
+        if (active) {
+            st(a.No, zc * E, us.n);
+            st(a.Fo, zc * E, us.fx);
+            st(a.Fo + V, zc * E, us.fy);
+            st(a.Fo + 2 * V, zc * E, us.fz);
+        }
+        // roll the window
+        if (z + 2 == nz && zhi_ghost) nn = ghost4(bd, 5, 0, c, nxt);
+        m1_pressure(nn.n, nn.fx, nn.fy, nn.fz, c, Pnn);
+        flo = fup;
+        cur = nxt;
+        nxt = nn;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            Pc[q] = Pn[q];
+            Pn[q] = Pnn[q];
+        }
+        hal = hal_next;
+        buf ^= 1;
+    }
+    if (DIAG) {
+        wave_count(a.cnt, CNT_LIMITER, nlim);
+        wave_count(a.cnt, CNT_NEG, nneg);
+    }
+}
+
 // FULL: every tile is a whole 64 x TY tile (nx % 64 == 0, ny % TY == 0), so
 // every thread owns a cell and no store needs a predicate.
 template <int G, typename R, bool DIAG, bool FUSE, bool FAST, int TY, int PD, bool FULL>
@@ -475,6 +720,28 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
         else
             hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, false>), dim3(nb),
                                dim3(kTX * TY), 0, st, a);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Split-path transport with the HLL flux: one launch per group.
+template <int G, typename S, bool DIAG>
+inline int launch_transport_tiled_hll(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
+                                      const ChemParams &cp, double lam, unsigned long long *cnt,
+                                      const Bounds<S> &bnd) {
+    constexpr int TY = 4;
+    const int LZ = pick_lz(gr, TY);
+    for (int g = 0; g < G; ++g) {
+        Bounds<S> bg = bnd;
+        for (int f = 0; f < 6; ++f) bg.phi[f][0] = bnd.phi[f][g];
+        TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
+                                        oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
+                                        GroupConsts{}, cp, lam, cnt, LZ, WorkList{}, TY, bg);
+        const int nb = a.ntx * a.nty * a.ntz;
+        if (gr.nx % kTX == 0 && gr.ny % TY == 0)
+            hipLaunchKernelGGL((k_tiled_hll<S, DIAG, TY, true>), dim3(nb), dim3(kTX * TY), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_tiled_hll<S, DIAG, TY, false>), dim3(nb), dim3(kTX * TY), 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

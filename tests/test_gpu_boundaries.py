@@ -26,6 +26,7 @@ CASES = {
     "inflow_yz": ((33, 7, 9), 1, [P, P, IN, TR, TR, IN], [0, 0, 2e6, 0, 0, 3e6]),
     "thin": ((1, 1, 64), 2, [TR, RF, RF, RF, RF, TR], None),
     "mixed_kinds": ((6, 5, 130), 4, [RF, TR, TR, RF, IN, TR], [0, 0, 0, 0, 1e6, 0]),
+    "whole_tiles": ((6, 8, 128), 2, [TR, TR, P, P, RF, IN], [0, 0, 0, 0, 0, 2e6]),
 }
 
 
@@ -74,9 +75,11 @@ def test_boundaries_match_oracle(name, precision, path):
         assert d["substeps"] == oc["substeps"] and d["limiter_hits"] == oc["limiter"]
 
 
+@pytest.mark.parametrize("path", ["reference", "split"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["transmissive", "inflow_x", "thin", "periodic"])
-def test_hll_reference_path_matches_oracle(name, precision):
+@pytest.mark.parametrize("name", ["transmissive", "inflow_x", "inflow_yz", "thin", "periodic", "reflective",
+                                  "mixed_kinds", "whole_tiles"])
+def test_hll_matches_oracle(name, precision, path):
     if name == "periodic":
         k = _case("reflective", 22)
         k["bc"], k["inflow"] = None, None
@@ -87,8 +90,8 @@ def test_hll_reference_path_matches_oracle(name, precision):
               flux="hll")
     ora = oracle.run(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"], **kw)
     gpu = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], k["cells"], k["rates"],
-                  precision=precision, path="reference", **kw)
-    _compare(gpu, ora, precision, f"hll {name}")
+                  precision=precision, path=path, **kw)
+    _compare(gpu, ora, precision, f"hll {name} {path}")
 
 
 @pytest.mark.parametrize("name", ["transmissive", "reflective", "inflow_x", "mixed_kinds", "thin"])
