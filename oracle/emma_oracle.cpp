@@ -68,8 +68,10 @@
  *       axis d the eigenvalues of the one-dimensional M1 system (N, F_d) at
  *       the normal reduced flux f_d = F_d/(c N) (clipped to [-1, 1], 0 when
  *       N <= 0): c (chi' +- sqrt(chi'^2 + 4 (chi - f_d chi')))/2, with chi
- *       and chi' = dchi/df at f_d; left speed min over both states and 0,
- *       right speed max over both states and 0.
+ *       and chi' = dchi/df at f_d, evaluated in the equal closed form
+ *       c (f_d +- 2 (s - 1)/sqrt(3))/s, s = sqrt(4 - 3 f_d^2) (m1_speeds);
+ *       left speed min over both states and 0, right speed max over both
+ *       states and 0.
  */
 #include <cmath>
 #include <cstdint>
@@ -232,24 +234,19 @@ void glf_flux(R NL, const R FL[3], R NR, const R FR[3], int d, double c,
         fluxF[k] = 0.5 * c * c * (PL[k][d] + PR[k][d]) - 0.5 * c * (FR[k] - FL[k]);
 }
 
-/* Levermore's chi and its derivative in f (R3), for the wave speeds. */
-template <class R> R chi_of(R f) { return (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f)); }
-template <class R> R dchi_df(R f) {
-    R s = sqrt(4.0 - 3.0 * f * f);
-    R den = 5.0 + 2.0 * s;
-    /* d/df of (3 + 4f^2)/(5 + 2s) with ds/df = -3f/s */
-    return (8.0 * f * den + (3.0 + 4.0 * f * f) * 6.0 * f / s) / (den * den);
-}
-
-/* Signal speeds along axis d of one state (R18). */
+/* Signal speeds along axis d of one state (R18).  With s = sqrt(4 - 3 f^2),
+ * chi = (3 + 4f^2)/(5 + 2s) gives chi' - 2f = 2f (1 - s)/s and
+ * chi - f^2 = (1 - s)^2/3, so the radicand chi'^2 + 4(chi - f chi') is
+ * 16 (s - 1)^2/(3 s^2) and the eigenvalues c (chi' +- sqrt(radicand))/2 are
+ * c (f +- 2 (s - 1)/sqrt(3))/s, with s - 1 = 3 (1 - f)(1 + f)/(1 + s): the
+ * same values without the cancellation of the radicand near |f| = 1. */
 template <class R> void m1_speeds(R N, const R F[3], int d, double c, R &lmin, R &lmax) {
     R f = R(0.0);
     if (N > R(0.0)) f = rmax(R(-1.0), rmin(R(1.0), F[d] / (c * N)));
-    R chi = chi_of(f), dchi = dchi_df(f);
-    /* the radicand is (1 - f)^2-small near |f| = 1 and may round below 0 */
-    R root = sqrt(rmax(R(0.0), dchi * dchi + 4.0 * (chi - f * dchi)));
-    lmin = 0.5 * c * (dchi - root);
-    lmax = 0.5 * c * (dchi + root);
+    const R s = sqrt(4.0 - 3.0 * f * f);
+    const R w = 3.4641016151377544 * (1.0 - f) * (1.0 + f) / (1.0 + s); /* 2 (s - 1)/sqrt(3) */
+    lmin = c * (f - w) / s;
+    lmax = c * (f + w) / s;
 }
 
 /* HLL flux across a face normal to axis d (R18):

@@ -130,8 +130,7 @@ __device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R P[6], R c) {
 // The HLL flux with M1 wave speeds (reference path: kernels.hpp k_transport)
 // does not split into per-cell parts: a face needs both sides' state U, flux
 // Ft_d = (F_d, c^2 P_xd, c^2 P_yd, c^2 P_zd) and speeds.  Each cell computes
-// its closure and its speeds along the three axes once (in double, as the
-// reference path does), publishes (U, Ft_x, Ft_y, speeds) in LDS for its x/y
+// its closure and its speeds along the three axes once, publishes (U, Ft_x, Ft_y, speeds) in LDS for its x/y
 // neighbours, keeps the z side in registers, and evaluates its own faces.
 template <typename R> struct Speeds2 {
     R lo, hi;  // min(0, lambda-), max(0, lambda+) along one axis
@@ -140,9 +139,9 @@ template <typename R> struct Speeds2 {
 template <typename R>
 __device__ __forceinline__ Speeds2<R> hll_speeds(const Vec4<R> &u, int d, R c) {
     const R fd = d == 0 ? u.fx : (d == 1 ? u.fy : u.fz);
-    double lmn, lmx;
-    m1_speeds<double>((double)u.n, (double)fd, (double)c, lmn, lmx);
-    return Speeds2<R>{(R)(lmn < 0.0 ? lmn : 0.0), (R)(lmx > 0.0 ? lmx : 0.0)};
+    R lmn, lmx;
+    m1_speeds<R>(u.n, fd, c, lmn, lmx);
+    return Speeds2<R>{lmn < R(0) ? lmn : R(0), lmx > R(0) ? lmx : R(0)};
 }
 
 template <typename R>

@@ -289,15 +289,13 @@ template <typename R>
 __device__ inline void hll(R NL, const R FL[3], const R PL[6], R NR, const R FR[3], const R PR[6], int d, R c,
                            R out[4]) {
     const int col[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-    // speeds in double: the radicand is O((1 - |f|)^2) from O(1) terms, which
-    // would leave sqrt(eps) errors in single precision
-    double lmL, lpL, lmR, lpR;
-    m1_speeds<double>(NL, FL[d], c, lmL, lpL);
-    m1_speeds<double>(NR, FR[d], c, lmR, lpR);
-    double amd = lmL < lmR ? lmL : lmR;
-    double apd = lpL > lpR ? lpL : lpR;
-    const R am = (R)(amd < 0.0 ? amd : 0.0);
-    const R ap = (R)(apd > 0.0 ? apd : 0.0);
+    R lmL, lpL, lmR, lpR;
+    m1_speeds<R>(NL, FL[d], c, lmL, lpL);
+    m1_speeds<R>(NR, FR[d], c, lmR, lpR);
+    const R amr = lmL < lmR ? lmL : lmR;
+    const R apr = lpL > lpR ? lpL : lpR;
+    const R am = amr < R(0) ? amr : R(0);
+    const R ap = apr > R(0) ? apr : R(0);
     const R inv = FastMath<R>::rcp(ap - am);
     const R cc = c * c, pm = ap * am;
     out[0] = (ap * FL[d] - am * FR[d] + pm * (NR - NL)) * inv;

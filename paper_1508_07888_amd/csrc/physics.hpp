@@ -96,9 +96,13 @@ __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) 
 
 // Signal speeds along one axis for the HLL flux: the eigenvalues of the
 // one-dimensional M1 system (N, F_d) -> (F_d, c^2 chi(f) N) at the normal
-// reduced flux f = F_d/(c N) in [-1, 1] (0 when N <= 0):
+// reduced flux f = F_d/(c N) in [-1, 1] (0 when N <= 0),
 //   lambda = c (chi' -+ sqrt(chi'^2 + 4 (chi - f chi')))/2.
-// The radicand is O((1 - |f|)^2) near |f| = 1 and is kept >= 0.
+// With s = sqrt(4 - 3 f^2), chi' - 2f = 2f (1 - s)/s and chi - f^2 =
+// (1 - s)^2/3, so the radicand is 16 (s - 1)^2/(3 s^2) and
+//   lambda = c (f -+ 2 (s - 1)/sqrt(3))/s,  s - 1 = 3 (1 - f)(1 + f)/(1 + s):
+// no cancellation near |f| = 1 (the radicand above is a difference of O(1)
+// terms that vanishes there), so single precision is enough.
 template <typename R>
 __device__ __forceinline__ void m1_speeds(R N, R Fd, R c, R &lmin, R &lmax) {
     using M = FastMath<R>;
@@ -108,16 +112,10 @@ __device__ __forceinline__ void m1_speeds(R N, R Fd, R c, R &lmin, R &lmax) {
         f = f < R(-1) ? R(-1) : (f > R(1) ? R(1) : f);
     }
     const R s = M::sqrt(R(4) - R(3) * f * f);
-    const R den = R(5) + R(2) * s;
-    const R iden = M::rcp(den);
-    const R num = R(3) + R(4) * f * f;
-    const R chi = num * iden;
-    const R dchi = (R(8) * f * den + R(6) * f * num * M::rcp(s)) * iden * iden;
-    R rad = dchi * dchi + R(4) * (chi - f * dchi);
-    rad = rad > R(0) ? rad : R(0);
-    const R root = M::sqrt(rad);
-    lmin = R(0.5) * c * (dchi - root);
-    lmax = R(0.5) * c * (dchi + root);
+    const R is = M::rcp(s);
+    const R w = R(3.4641016151377544) * (R(1) - f) * (R(1) + f) * M::rcp(R(1) + s);  // 2 (s - 1)/sqrt(3)
+    lmin = c * (f - w) * is;
+    lmax = c * (f + w) * is;
 }
 
 // ------------------------------------------------------------------- rates

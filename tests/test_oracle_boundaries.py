@@ -288,3 +288,28 @@ def test_hll_conserves_photons_and_stays_realisable():
         assert cnt["neg_clamp"] == 0 and N.min() >= 0
         assert np.all(np.linalg.norm(F, axis=1) <= c * N * (1 + 1e-12) + 1e-300)
     assert np.allclose(N.reshape(2, -1).sum(axis=1), tot0, rtol=1e-13, atol=0)
+
+
+def test_m1_speeds_equal_the_printed_eigenvalue_form_near_free_streaming():
+    # c (chi' +- sqrt(chi'^2 + 4 (chi - f chi')))/2 evaluated with 60 digits
+    # from Levermore's chi (R3) and its derivative, against the oracle's
+    # cancellation-free form, down to |f| = 1 - 1e-12 where the printed
+    # radicand is a difference of O(1) terms of size 1e-24
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    c = 0.1 * C
+    N = 2.0
+    for f in (0.0, 0.3, -0.77, 0.999, -0.999999, 1 - 1e-9, -(1 - 1e-12), 1.0):
+        fd = Decimal(f)
+        s = (4 - 3 * fd * fd).sqrt()
+        den = 5 + 2 * s
+        num = 3 + 4 * fd * fd
+        chi = num / den
+        dchi = (8 * fd * den + 6 * fd * num / s) / (den * den)
+        root = (dchi * dchi + 4 * (chi - fd * dchi)).sqrt()
+        want = [float(Decimal(c) * (dchi - root) / 2), float(Decimal(c) * (dchi + root) / 2)]
+        got = oracle.m1_speeds(N, [f * c * N, 0.0, 0.0], 0, c)
+        for g, w in zip(got, want):
+            # f itself is rebuilt from F / (c N) (an ulp off), and the
+            # speeds change by about 4.5 c per unit of f near |f| = 1
+            assert abs(g - w) <= 2e-15 * c, (f, got, want)
