@@ -701,9 +701,15 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     S *Ut = (S *)c->Ns, *Ft = (S *)c->Fs;
     for (int s = n_steps - 1; s >= 0; --s) {
         {
+            // the transport of step s again, before the floor and the limiter,
+            // with the forward's own kernel arithmetic
             Timed t(c, KID_ADJ_FWD);
-            hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3(nblk), dim3(tb), 0, c->stream, tN(s), tF(s),
-                               Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+            if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
+                hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3(nblk), dim3(tb), 0, c->stream, tN(s),
+                                   tF(s), Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+            else
+                launch_transport_tiled<G, S, false>(c->stream, tN(s), tF(s), Ut, Ft, gr, cp, lam, c->cnt,
+                                                    bounds_of<S>(c), true);
         }
         if (int e = check_launch(c, "k_transport (adjoint recompute)")) return e;
         if (int e = reset_worklist(c)) return e;

@@ -61,6 +61,7 @@ template <typename R> struct TileArgs {
     unsigned long long *cnt;
     WorkList wl;
     Bounds<R> bnd;
+    int nolimit;  // 1: write the values before the N >= 0 floor and the limiter (split transport)
 };
 
 template <typename R> struct alignas(4 * sizeof(R) > 16 ? 16 : 4 * sizeof(R)) Vec4 {
@@ -562,13 +563,15 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
                 R fx = cur[g].fx + hl * ((aL.fx + bR.fx) + (aD.fx + bT.fx) + (Az2[g].fx + Bz2[g].fx) - s6 * cur[g].fx);
                 R fy = cur[g].fy + hl * ((aL.fy + bR.fy) + (aD.fy + bT.fy) + (Az2[g].fy + Bz2[g].fy) - s6 * cur[g].fy);
                 R fz = cur[g].fz + hl * ((aL.fz + bR.fz) + (aD.fz + bT.fz) + (Az2[g].fz + Bz2[g].fz) - s6 * cur[g].fz);
-                if (n < R(0)) { n = R(0); if (active) nneg++; }
-                const R F2 = fx * fx + fy * fy + fz * fz;
-                const R cn = c * n;
-                if (F2 > cn * cn) {
-                    const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
-                    fx *= sc; fy *= sc; fz *= sc;
-                    if (active) nlim++;
+                if (!a.nolimit) {
+                    if (n < R(0)) { n = R(0); if (active) nneg++; }
+                    const R F2 = fx * fx + fy * fy + fz * fz;
+                    const R cn = c * n;
+                    if (F2 > cn * cn) {
+                        const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
+                        fx *= sc; fy *= sc; fz *= sc;
+                        if (active) nlim++;
+                    }
                 }
                 us[g] = Vec4<R>{n, fx, fy, fz};
             }
@@ -682,6 +685,7 @@ inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, 
     a.cnt = cnt;
     a.wl = wl;
     a.bnd = bnd;
+    a.nolimit = 0;
     return a;
 }
 
@@ -702,7 +706,7 @@ inline bool tiled_supported(const Grid &gr) { return (uint64_t)gr.V * 8 < ((uint
 template <int G, typename S, bool DIAG>
 inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
                                   const ChemParams &cp, double lam, unsigned long long *cnt,
-                                  const Bounds<S> &bnd) {
+                                  const Bounds<S> &bnd, bool nolimit = false) {
     // double tiles need twice the LDS: at most 8 rows (136 KB)
     constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
     const int LZ = pick_lz(gr, TY);
@@ -712,6 +716,7 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
         TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
                                         oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
                                         GroupConsts{}, cp, lam, cnt, LZ, WorkList{}, TY, bg);
+        a.nolimit = nolimit ? 1 : 0;
         const int nb = a.ntx * a.nty * a.ntz;
         if (gr.nx % kTX == 0 && gr.ny % TY == 0)
             hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, true>), dim3(nb),
