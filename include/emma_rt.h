@@ -170,8 +170,8 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
  *                   index (cz ratio + cy) ratio + cx within the parent
  *   n_fine          device double [n_ref][ratio^3], read only
  * Child sources have density rate * src_frac / (dx / ratio)^3.  The transport
- * uses the split path's tiled kernel (fused and split paths) or the reference
- * kernel (reference path).  Entries of ref_cell outside the grid or repeated,
+ * uses the split path's tiled kernel (fused and split paths; the tiled HLL
+ * kernel with EMMA_RT_FLUX_HLL) or the reference kernel (reference path).  Entries of ref_cell outside the grid or repeated,
  * and source children outside 0..ratio^3-1, are ignored and reported as
  * EINVAL when diag is given.  No adjoint.  Returns as emma_rt_step, and EINVAL
  * for ratio not 2 or 4 or NULL arrays with n_ref > 0. */
