@@ -44,6 +44,8 @@ def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1508_07888_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
+        if not f.endswith((".hip", ".hpp")):
+            continue
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())

@@ -119,3 +119,26 @@ def test_rate_fits_match_oracle():
             # evaluated as exp(argument) with |argument| up to ~600 here: the
             # relative error grows with the argument's size
             assert abs(beta / ob["beta"] - 1) < 4e-16 * (10 + abs(np.log(ob["beta"])))
+
+
+def test_polynomial_coefficients_are_the_generated_ones():
+    """The exp/log coefficients in fastmath.hpp are those fastmath_coeffs.py
+    computes (Chebyshev interpolants in 50-digit arithmetic), and the stated
+    interpolation errors hold."""
+    import importlib.util
+    import re
+    pytest.importorskip("mpmath")
+    spec = importlib.util.spec_from_file_location("fastmath_coeffs", os.path.join(CSRC, "fastmath_coeffs.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    c = gen.coefficients()
+    src = open(os.path.join(CSRC, "fastmath.hpp")).read()
+
+    def hexes(fn):
+        body = src[src.index(fn):]
+        body = body[:body.index("return")]
+        return [float.fromhex(h) for h in re.findall(r"0x1\.[0-9a-f]+p[-+]?\d+", body)]
+
+    assert hexes("double exp_fp64(") == c["exp"][:-2] and c["exp"][-2:] == [1.0, 1.0]
+    assert hexes("double log_fp64(") == c["log"]
+    assert c["exp_err"] < 4e-18 and c["log_err"] < 2e-16
