@@ -41,3 +41,12 @@ def test_committed_counter_summaries_follow_the_sources(tmp_path, monkeypatch):
     (prof / "chemistry_w_mixed_pmc.json").write_text(json.dumps(d))
     assert bench.traffic_from_profiles("chemistry", "w", "mixed") == 1.0
     assert bench.valu_from_profiles("void emma::k_chem<3") is None  # no SQ summary there
+
+
+def test_valu_issue_fractions_against_a_hand_count():
+    # one wave per SIMD, each issuing 2.4e6 instructions of 4 cycles over 4 ms
+    # at 2.4 GHz fills all the SIMDs' cycles; the active count (units of 4
+    # cycles) likewise
+    cv = {"valu_instr_per_wave": 2.4e6, "valu_active_per_wave": 1.2e6}
+    f = bench.valu_issue(cv, bench.SIMDS, 4e-3)
+    assert abs(f["valu_issue_frac"] - 1.0) < 1e-12 and abs(f["valu_active_frac"] - 0.5) < 1e-12
