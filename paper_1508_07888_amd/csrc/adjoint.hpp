@@ -518,8 +518,13 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
 // or 4 substeps (replayed from the cell's start) measured slower: 3.7 and
 // 4.3 ms per step at 256^3 against 2.4 ms for this split before the
 // single-substep form.
+// one wave per block, for the reason given at EMMA_CHEM_TB (1.21 ms against
+// 1.29 ms with 256 threads at 256^3)
+#ifndef EMMA_ADJ_TB
+#define EMMA_ADJ_TB 64
+#endif
 template <int G, typename S, bool FAST>
-__global__ __launch_bounds__(256) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
+__global__ __launch_bounds__(EMMA_ADJ_TB) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
                                                   const double *__restrict__ xs, const double *__restrict__ Ts,
                                                   const double *__restrict__ n0, int64_t V, SrcTable src,
                                                   GroupConsts gc, ChemParams cp, const S *__restrict__ gN,

@@ -331,7 +331,7 @@ static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, dou
                        const uint32_t *skip) {
     const int64_t V = c->grid.V;
     const WorkList wl{c->work_count, c->work_cells};
-    const int tb = 256;
+    const int tb = chem_tb<S>();
     hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST>), dim3((unsigned)((V + tb - 1) / tb)), dim3(tb), 0, c->stream, Ns,
                        Fs, N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, skip);
     return check_launch(c, "chemistry");
@@ -716,11 +716,13 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
         {
             Timed t(c, KID_ADJ_CHEM);
             const WorkList wl{c->work_count, c->work_cells};
+            const int atb = EMMA_ADJ_TB;
+            const unsigned ablk = (unsigned)((V + atb - 1) / atb);
             if (fast)
-                hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
+                hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
                                    tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
             else
-                hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, Ut, Ft, tx(s),
+                hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
                                    tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
             if (int e = check_launch(c, "k_chem_adj")) return e;
         }

@@ -419,6 +419,20 @@ __device__ inline void defer_push(const WorkList &wl, bool defer, uint32_t i) {
 #ifndef EMMA_CHEM_MIN_BLOCKS
 #define EMMA_CHEM_MIN_BLOCKS 1
 #endif
+// Threads per block of the first chemistry pass.  With FP32 storage, one
+// wave: its waves run for different times (one substep or several); a
+// one-wave block reuses the slot of a wave that finished early at once, where
+// a four-wave block has to wait for room for all four (measured at 256^3:
+// 0.507 ms against 0.574 ms with 256 threads, 0.514 ms with 128).  The FP64
+// variant measured the other way (0.730 ms with 64 threads against 0.694 ms
+// with 256) and keeps four-wave blocks.
+#ifndef EMMA_CHEM_TB
+#define EMMA_CHEM_TB 64
+#endif
+#ifndef EMMA_CHEM_TB_FP64
+#define EMMA_CHEM_TB_FP64 256
+#endif
+template <typename S> constexpr int chem_tb() { return sizeof(S) == 4 ? EMMA_CHEM_TB : EMMA_CHEM_TB_FP64; }
 
 template <typename T>
 __device__ __forceinline__ T stream_ld(const T *p) {
@@ -436,7 +450,7 @@ __device__ __forceinline__ void stream_st(T *p, T v) {
 // or defers the cell (budget exhausted: nothing written).  F_out = F* Pf with
 // Pf the product of the substeps' factors, as in chem_cell.
 template <int G, typename S, bool DIAG, bool FAST>
-__global__ __launch_bounds__(256, EMMA_CHEM_MIN_BLOCKS) void k_chem(
+__global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
     const S *__restrict__ Ns, const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
     double *__restrict__ x, double *__restrict__ T, const double *__restrict__ n0, int64_t V, SrcTable src,
     GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, const uint32_t *__restrict__ skip) {
