@@ -62,6 +62,8 @@ def lib():
         L.oracle_rates.restype = None
         L.oracle_rates.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, _dp]
+        L.oracle_rate_coeffs.restype = None
+        L.oracle_rate_coeffs.argtypes = [ctypes.c_double, _dp]
         L.oracle_cross_section.restype = ctypes.c_double
         L.oracle_cross_section.argtypes = [ctypes.c_double]
         L.oracle_group_constants.restype = None
@@ -243,6 +245,14 @@ def rates(T, n0=1.0, x=0.5, otsa=1):
     out = np.empty(4, dtype=np.float64)
     lib().oracle_rates(float(T), float(n0), float(x), int(otsa), _d(out))
     return {"alpha_A": out[0], "alpha_B": out[1], "beta": out[2], "Lambda": out[3]}
+
+
+def rate_coeffs(T):
+    """The individual fits at T: alpha_A, alpha_B, beta (cm^3/s), rec_A, rec_B
+    (recombination cooling), cexc (collisional excitation), brems (erg cm^3/s)."""
+    out = np.empty(7, dtype=np.float64)
+    lib().oracle_rate_coeffs(float(T), _d(out))
+    return dict(zip(("alpha_A", "alpha_B", "beta", "rec_A", "rec_B", "cexc", "brems"), out))
 
 
 def cross_section(E_eV):

@@ -820,6 +820,21 @@ void oracle_rates(double T, double n0, double x, int otsa, double *out) {
     out[3] = cooling<double>(r, n0, x, otsa);
 }
 
+/* The seven rate coefficients at temperature T, in the order alpha_A,
+ * alpha_B, beta (cm^3 s^-1), recombination cooling case A and case B,
+ * collisional excitation, bremsstrahlung (erg cm^3 s^-1): read-only access
+ * for the pins of the individual fits. */
+void oracle_rate_coeffs(double T, double *out) {
+    Rates<double> r = rates_at<double>(T);
+    out[0] = r.alphaA;
+    out[1] = r.alphaB;
+    out[2] = r.beta;
+    out[3] = r.recA;
+    out[4] = r.recB;
+    out[5] = r.cexc;
+    out[6] = r.brems;
+}
+
 double oracle_cross_section(double E_eV) { return cross_section(E_eV); }
 
 void oracle_group_constants(double Tbb, const double *edges_eV, int G, int panels,

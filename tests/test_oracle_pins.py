@@ -250,6 +250,163 @@ def test_rate_anchors():
     assert abs(math.log(s2 / s1) / math.log(2.0) + 3.5) < 0.02
 
 
+# The rate compilations named in Sec. 2.2.4 are not printed; these pins fix
+# each fit by what the atomic physics and the standard tables say, so that a
+# wrong exponent, coefficient or density power in any of them fails here.
+
+def _log_slope_inv_T(name, T, h=1e-5):
+    """d ln(rate) / d(1/T) by a central difference in 1/T."""
+    u = 1.0 / T
+    hi = oracle.rate_coeffs(1.0 / (u * (1 + h)))[name]
+    lo = oracle.rate_coeffs(1.0 / (u * (1 - h)))[name]
+    return (math.log(hi) - math.log(lo)) / (2 * h * u)
+
+
+def test_collisional_ionisation_is_arrhenius_with_the_ionisation_potential():
+    # At T << T_HI the collisional ionisation rate is dominated by the
+    # Boltzmann factor exp(-13.6 eV / k_B T): d ln beta / d(1/T) -> -T_HI.
+    T_HI = 13.6 * EV / KB
+    for T, tol in ((500.0, 0.0025), (1000.0, 0.005)):
+        assert abs(_log_slope_inv_T("beta", T) / -T_HI - 1) < tol
+
+
+def test_collisional_ionisation_magnitude_against_cen_1992():
+    # An independent fit of the same process (Cen 1992):
+    # 5.85e-11 T^1/2 exp(-157809.1/T) / (1 + (T/1e5)^1/2) cm^3/s.  The two
+    # compilations differ by less than a factor 3 over 1e4-1e6 K.
+    for T in (1e4, 3e4, 1e5, 3e5, 1e6):
+        cen = 5.85e-11 * math.sqrt(T) * math.exp(-157809.1 / T) / (1 + math.sqrt(T / 1e5))
+        assert 1.0 / 3.0 < oracle.rate_coeffs(T)["beta"] / cen < 3.0
+
+
+def test_collisional_excitation_is_boltzmann_at_the_lyman_alpha_energy():
+    # Excitation of n = 2 costs 3/4 of 13.6 eV: its Boltzmann temperature is
+    # 118,366 K, which the excitation cooling's slope must show at low T.
+    T_lya = 0.75 * 13.6 * EV / KB
+    for T in (500.0, 1000.0):
+        assert abs(_log_slope_inv_T("cexc", T) / -T_lya - 1) < 1e-3
+
+
+def test_collisional_excitation_falls_as_inverse_root_temperature_when_hot():
+    # A collision rate has the form q ~ Omega T^-1/2 exp(-dE / k_B T) with a
+    # slowly varying collision strength Omega: far above the excitation
+    # temperature the excitation coefficient falls about as T^-1/2.
+    for T in (1e7, 1e8):
+        slope = -_log_slope_inv_T("cexc", T) / T  # d ln q / d ln T
+        assert abs(slope + 0.5) < 0.1
+
+
+def test_each_collisional_ionisation_removes_the_ionisation_energy():
+    # In Lambda = A n_e n_p + B n_e n_HI the n_e n_HI part is collisional
+    # excitation plus collisional ionisation, and every collisional
+    # ionisation removes the ionisation energy from the gas:
+    # B - cexc = E_ion beta (E_ion = 13.598 eV, which Sec. 2.2.4 rounds to
+    # 13.6 eV; hence the 2e-4 allowance).
+    for T in (5e4, 1e5, 3e5, 1e6):
+        r = oracle.rate_coeffs(T)
+        A = oracle.rates(T, 1.0, 1.0)["Lambda"]            # n_HI = 0
+        for x in (0.25, 0.5):
+            B = (oracle.rates(T, 1.0, x)["Lambda"] - A * x * x) / (x * (1 - x))
+            assert abs((B - r["cexc"]) / (13.6 * EV * r["beta"]) - 1) < 2e-4
+
+
+def test_recombination_coefficients_against_osterbrock_table():
+    # Osterbrock & Ferland, Table 2.1 (hydrogen): alpha_B = 4.54, 2.59, 1.43
+    # and alpha_A = 6.82, 4.18, 2.51 (1e-13 cm^3/s) at 5000, 10^4, 2x10^4 K.
+    for T, aB, aA in ((5000.0, 4.54e-13, 6.82e-13), (1e4, 2.59e-13, 4.18e-13),
+                      (2e4, 1.43e-13, 2.51e-13)):
+        r = oracle.rate_coeffs(T)
+        assert abs(r["alpha_B"] / aB - 1) < 0.005
+        assert abs(r["alpha_A"] / aA - 1) < 0.04
+
+
+def test_recombination_cooling_per_recombination_is_below_the_mean_thermal_energy():
+    # Slow electrons recombine preferentially, so the kinetic energy removed
+    # per recombination is a fraction of k_B T and below the mean 3/2 k_B T,
+    # falling with T (both cases).
+    prev = {"B": 2.0, "A": 2.0}
+    for T in (1e2, 1e3, 1e4, 1e5, 1e6):
+        r = oracle.rate_coeffs(T)
+        for case in ("A", "B"):
+            e = r["rec_" + case] / r["alpha_" + case] / (KB * T)
+            assert 0.2 < e < 1.5
+            assert e < prev[case]
+            prev[case] = e
+
+
+def test_cooling_scales_with_density_squared_and_needs_electrons():
+    # Every cooling channel is a two-body rate, n_e n_p or n_e n_HI.
+    for T in (3e3, 2e4, 1e6):
+        for x in (1e-3, 0.3, 0.9, 1.0):
+            L1 = oracle.rates(T, 1e-3, x)["Lambda"]
+            L7 = oracle.rates(T, 7e-3, x)["Lambda"]
+            assert abs(L7 / (49 * L1) - 1) < 1e-13
+        assert oracle.rates(T, 1e-3, 0.0)["Lambda"] == 0.0
+
+
+def test_hot_ionised_gas_cools_by_bremsstrahlung():
+    # Fully ionised gas well above the hydrogen lines: free-free emission,
+    # Lambda proportional to T^1/2 n_e n_p.
+    L1 = oracle.rates(1e8, 1.0, 1.0)["Lambda"]
+    L4 = oracle.rates(4e8, 1.0, 1.0)["Lambda"]
+    assert abs(L4 / L1 - 2.0) < 2e-3
+
+
+def test_collisional_ionisation_equilibrium_cooling_peak():
+    # The optically thin cooling curve of hydrogen in collisional ionisation
+    # equilibrium (x = beta / (alpha_A + beta), no radiation) peaks at
+    # Lambda / n_H^2 ~ 1e-22 erg cm^3/s near 2e4 K, where collisional
+    # excitation of the remaining neutral atoms dominates.  The peak's height
+    # fixes the excitation coefficient, its position the balance of
+    # collisional ionisation and recombination.
+    Ts = np.logspace(3.8, 5.2, 281)
+    L = []
+    for T in Ts:
+        r = oracle.rate_coeffs(T)
+        x = r["beta"] / (r["alpha_A"] + r["beta"])
+        L.append(oracle.rates(T, 1.0, x, otsa=0)["Lambda"])
+    i = int(np.argmax(L))
+    assert 1.2e4 < Ts[i] < 3e4
+    assert 5e-23 < L[i] < 2e-22
+
+
+def test_cross_section_formula_meets_its_threshold_value():
+    # Sec. 2.2.3 groups the hydrogenic cross-section; just above 13.6 eV the
+    # formula itself (not the special case at threshold) gives 6.30e-18 cm^2.
+    for d in (1e-9, 1e-7):
+        s = oracle.cross_section(13.6 * (1 + d))
+        assert abs(s / 6.30e-18 - 1) < 10 * d
+
+
+def test_cross_section_obeys_the_continuum_oscillator_strength_sum_rule():
+    # Thomas-Reiche-Kuhn for hydrogen 1s: the bound lines carry 0.565 of the
+    # oscillator strength and the continuum 0.435, so
+    # int sigma dnu = (pi e^2 / m_e c) 0.435 (the 6.30e-18 threshold value is
+    # rounded from 6.304e-18, hence the 0.2 % allowance).
+    from scipy.integrate import quad
+    h = 6.62607015e-27
+    e, me = 4.80320471e-10, 9.1093837e-28
+    f = lambda lnE: oracle.cross_section(math.exp(lnE)) * math.exp(lnE)
+    I_eV = quad(f, math.log(13.6 * (1 + 1e-12)), math.log(13.6e6), limit=500, epsrel=1e-10)[0]
+    f_cont = I_eV * EV / h / (math.pi * e * e / (me * C))
+    assert abs(f_cont / 0.435 - 1) < 2e-3
+
+
+@pytest.mark.parametrize("G, sigma_N, mean_eV, frac", [
+    (1, [1.625e-18], [29.61], [1.0]),
+    (3, [2.995e-18, 5.682e-19, 7.877e-20], [18.86, 35.08, 65.64], [0.4474, 0.4940, 0.0586]),
+])
+def test_group_constants_table(G, sigma_N, mean_eV, frac):
+    # Group constants of eq. (e:siggroup) for the 1e5 K black body with the
+    # edges 13.6 / 24.6 / 54.4 / 1000 eV, tabulated by an independent
+    # quadrature of the same spectrum and cross-section, to its printed digits.
+    g = _groups(G)
+    for i in range(G):
+        assert abs(g["sigma_N"][i] / sigma_N[i] - 1) < 0.5e-3 * 1.01
+        assert abs(g["mean_E"][i] / EV - mean_eV[i]) <= 0.005 * 1.01
+        assert abs(g["frac"][i] - frac[i]) <= 0.00005 * 1.01
+
+
 def _bb_number(a):
     # int_a^inf x^2/(e^x - 1) dx in closed series form
     return sum(math.exp(-k * a) * (a * a / k + 2 * a / k ** 2 + 2 / k ** 3) for k in range(1, 400))
