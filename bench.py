@@ -35,9 +35,22 @@ def algorithmic_bytes(kernel, G, elem):
     nf = 4 * G * elem
     if kernel == "transport":
         return 2 * nf
-    if kernel in ("chemistry", "fused_step"):
+    if kernel in ("chemistry", "fused_step", "step"):
         return 2 * nf + 3 * 8 + 2 * 8
     return None
+
+
+def kernel_fracs(kern, G, elem, V):
+    """Each timed kernel's algorithmic bytes per step over its own measured
+    time per step, as a fraction of the HBM peak (transport: N, F in and out;
+    chemistry and the fused step: the whole state in and out plus n0)."""
+    out = {}
+    for k, (n, ms) in kern.items():
+        b = algorithmic_bytes(k, G, elem)
+        if b is None or ms <= 0:
+            continue
+        out[k] = b * V / (ms / n * 1e-3) / HBM_PEAK
+    return out
 
 
 def source_hash():
@@ -465,18 +478,120 @@ def rt_scratch_gb(w, precision, K):
     return _lib.emma_rt_scratch_bytes(cfg) / 1e9
 
 
-def cpu_baseline(w, budget_steps=1):
-    """The oracle, untuned and serial, on the first step of the same inputs."""
+# The CPU baseline: the serial FP64 oracle as it stands, one process per leg,
+# each single-threaded.  Legs: the parity build (-O2 -ffp-contract=off) and a
+# timing-only build (-O3 -march=native, compiled here for this host), each on
+# the first steps of the benchmark's 256^3 inputs (truncated: the whole
+# 50-step run is ~10 min per build) and on the whole 128^3, 100-step workload;
+# then a replicated aggregate: one independent oracle process per usable core
+# (at most 16) on the first steps of the 128^3 workload, summed.
+CPU_LEGS = (("throughput256", 5, "O2"), ("throughput256", 5, "O3native"),
+            ("lognormal128", 100, "O2"), ("lognormal128", 100, "O3native"))
+REPLICATED_STEPS = 10
+
+
+def cpu_leg(workload, steps, lib_path):
+    """One leg, run in a child process: prints its JSON line."""
     import oracle
+    if lib_path:
+        oracle.use_library(lib_path)
+    import emma_inputs as E
+    w = E.make_workload(workload)
     g = oracle.group_constants(w["T_bb"], w["edges"])
     t = time.perf_counter()
     oracle.run(w["N"], w["F"], w["x"], w["T"], w["n0"], w["src_cell"], w["src_rate"],
-               dx=w["dx"], c_red=w["c_red"], dt=w["dt"], n_steps=budget_steps, groups=g)
+               dx=w["dx"], c_red=w["c_red"], dt=w["dt"], n_steps=steps, groups=g)
     s = time.perf_counter() - t
-    V = w["n0"].size
-    return {"value": V * budget_steps / s, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {budget_steps} step(s) of the same {w['shape'][0]}^3 inputs, "
-                      f"serial FP64 oracle (g++ -O2), {s:.1f} s"}
+    cu = w["n0"].size * steps
+    print(json.dumps({"workload": workload, "steps": steps, "of_steps": w["steps"], "seconds": s,
+                      "cell_updates_per_s": cu / s}), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+class CpuBaseline:
+    """Starts the CPU legs as child processes (they run while the GPU is
+    timed: one core each), then collects them and runs the replicated leg."""
+
+    def __init__(self, mode):
+        import subprocess
+        import tempfile
+        from oracle import build as obuild
+        self.mode = mode
+        self.tmp = tempfile.mkdtemp(prefix="emma_oracle_")
+        self.libs = {"O2": None}
+        if mode == "full":
+            self.libs["O3native"] = obuild.build_timing(os.path.join(self.tmp, "liboracle_o3native.so"))
+            legs = CPU_LEGS
+        else:
+            legs = (("throughput256", 1, "O2"),)
+        self.procs = []
+        for wl, steps, build in legs:
+            cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", wl, str(steps), self.libs[build] or ""]
+            self.procs.append(((wl, steps, build), subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)))
+
+    def _collect(self, procs):
+        out = {}
+        for (wl, steps, build), p in procs:
+            o, _ = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError(f"CPU leg {wl}/{steps}/{build} failed ({p.returncode})")
+            out[(wl, steps, build)] = json.loads(o.strip().splitlines()[-1])
+            print(f"cpu leg done: {wl} {steps} steps, {build}, {out[(wl, steps, build)]['seconds']:.1f} s",
+                  file=sys.stderr, flush=True)
+        return out
+
+    def finish(self):
+        import shutil
+        import subprocess
+        res = self._collect(self.procs)
+        legs = {}
+        for (wl, steps, build), r in res.items():
+            trunc = r["steps"] < r["of_steps"]
+            legs[f"{wl}_{build}"] = {
+                "cell_updates_per_s": r["cell_updates_per_s"], "seconds": r["seconds"], "steps": r["steps"],
+                "of_steps": r["of_steps"], "truncated": trunc,
+                "build": "g++ -O2 -ffp-contract=off (parity build)" if build == "O2"
+                         else "g++ -O3 -march=native (timing build)"}
+        main = res[("throughput256", 5 if self.mode == "full" else 1, "O2")]
+        cpus = os.cpu_count()
+        try:
+            usable = len(os.sched_getaffinity(0))
+        except AttributeError:
+            usable = cpus
+        out = {"value": main["cell_updates_per_s"], "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {main['steps']} of the {main['of_steps']} steps of the same 256^3 inputs "
+                         f"(truncated), serial FP64 oracle, parity build (g++ -O2 -ffp-contract=off), "
+                         f"{main['seconds']:.1f} s on one core",
+               "cpu_model": _cpu_model(), "cpu_count": cpus, "usable_cores": usable, "legs": legs}
+        if self.mode == "full":
+            P = max(1, min(usable, 16))
+            cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "lognormal128", str(REPLICATED_STEPS),
+                   self.libs["O3native"]]
+            t = time.perf_counter()
+            procs = [(("lognormal128", REPLICATED_STEPS, f"rep{k}"),
+                      subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)) for k in range(P)]
+            rep = self._collect(procs)
+            wall = time.perf_counter() - t
+            V = 128 ** 3
+            out["replicated"] = {
+                "processes": P, "aggregate_cell_updates_per_s": P * V * REPLICATED_STEPS / wall,
+                "per_process_mean": statistics.mean(r["cell_updates_per_s"] for r in rep.values()),
+                "wall_s": wall,
+                "label": f"aggregate throughput of {P} independent serial oracle processes (timing build), "
+                         f"each on the first {REPLICATED_STEPS} steps of the 128^3 workload: a replicated "
+                         "figure, not a parallel code"}
+        shutil.rmtree(self.tmp, ignore_errors=True)
+        return out
 
 
 def main():
@@ -486,7 +601,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="throughput256")
     ap.add_argument("--n", type=int, default=None, help="override the grid size")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="same as --cpu-baseline none")
+    ap.add_argument("--cpu-baseline", default="full", choices=["full", "quick", "none"],
+                    help="full: parity and -O3 builds on the truncated 256^3 run and the whole 128^3 run, "
+                         "plus the replicated aggregate; quick: one step of the 256^3 run, parity build")
+    ap.add_argument("--cpu-leg", nargs=3, metavar=("WORKLOAD", "STEPS", "LIB"), help=argparse.SUPPRESS)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--variants", action="store_true",
                     help="also time the other paths and options (fused, reference, HLL, open boundaries, "
@@ -509,6 +628,9 @@ def main():
                     help="output file for --summarize-trace, output directory for --summarize-pmc")
     ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg(args.cpu_leg[0], int(args.cpu_leg[1]), args.cpu_leg[2])
+        return
     if args.summarize_pmc:
         out = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, "mixed",
                             args.summary_out or os.path.join(ROOT, "profiles"), args.command)
@@ -528,6 +650,9 @@ def main():
     import emma_inputs as E
     w = E.make_workload(args.workload, n=args.n)
     G = w["G"]
+    cpu_mode = "none" if args.no_cpu_baseline else args.cpu_baseline
+    # the CPU legs run on their own cores while the GPU is timed
+    cpu = CpuBaseline(cpu_mode) if cpu_mode != "none" else None
     if args.copy_calibration:
         copy_calibration()
     mixed = run_gpu(w, "mixed", args.steps, args.warmup, args.path, args.reps)
@@ -541,9 +666,15 @@ def main():
     bytes_launch = per_cell * mixed["V"]
     achieved = bytes_launch / avg_s
     traffic = traffic_from_profiles(dom, args.workload, "mixed")
+    # the whole step against the same roofline: cell-updates/s x algorithmic
+    # bytes per cell-update (the state in and out once, n0 read) / peak
+    step_bytes = algorithmic_bytes("step", G, mixed["elem"])
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic, "kernel": dom,
-                "bytes_per_cell": per_cell, "avg_launch_ms": avg_s * 1e3}
+                "bytes_per_cell": per_cell, "avg_launch_ms": avg_s * 1e3,
+                "step_frac": mixed["value"] * step_bytes / HBM_PEAK,
+                "step_achieved": mixed["value"] * step_bytes / 1e9, "step_bytes_per_cell": step_bytes,
+                "kernels_frac": kernel_fracs(kern, G, mixed["elem"], mixed["V"])}
     # the SQ counter summary is of the default command (this workload, split path)
     chem_valu = None
     if args.workload == "throughput256" and args.path == "split":
@@ -583,17 +714,19 @@ def main():
         dom64 = max((k for k in k64 if k != "src_table"), key=lambda k: k64[k][1])
         b64 = algorithmic_bytes(dom64, G, 8) * fp64["V"]
         a64 = b64 / (k64[dom64][1] / k64[dom64][0] * 1e-3)
+        sb64 = algorithmic_bytes("step", G, 8)
         out["fp64"] = {"value": fp64["value"], "ms_per_step": fp64["ms_per_step"], "repetitions": fp64["reps"],
                        "dtype": "f64", "kernel": dom64, "achieved_GBs": a64 / 1e9,
-                       "frac": a64 / HBM_PEAK,
+                       "frac": a64 / HBM_PEAK, "step_frac": fp64["value"] * sb64 / HBM_PEAK,
+                       "step_bytes_per_cell": sb64, "kernels_frac": kernel_fracs(k64, G, 8, fp64["V"]),
                        "kernels_ms": {k: v[1] / v[0] for k, v in k64.items()}}
         out["mixed_over_fp64"] = mixed["value"] / fp64["value"]
     if args.variants:
         out["variants"] = run_variants(w)
     if args.adjoint:
         out["adjoint"] = {p: run_adjoint(w, p) for p in (("mixed",) if args.no_fp64 else ("mixed", "fp64"))}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu.finish()
     print(json.dumps(out), flush=True)
 
 

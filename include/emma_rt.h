@@ -76,7 +76,7 @@ typedef enum { EMMA_RT_FLUX_GLF = 0, EMMA_RT_FLUX_HLL = 1 } emma_rt_flux;
 #define EMMA_RT_MAX_SOURCES 65536
 
 typedef struct {
-    int32_t nx, ny, nz;         /* grid, each >= 1 */
+    int32_t nx, ny, nz;         /* grid, each >= 1, at most 2^32 - 1 cells in all */
     int32_t n_groups;           /* 1 .. EMMA_RT_MAX_GROUPS frequency groups */
     double dx;                  /* cell size, cm */
     double c_red;               /* reduced speed of light (Sec. 2.2.3), 0 < c_red <= c */
@@ -142,7 +142,9 @@ int emma_rt_init(emma_rt_ctx **ctx, const emma_rt_config *cfg, void *hip_stream)
  *   N, F            device, float or double per precision, read and written
  *   x_HII, T        device double, read and written
  *   n_H             device double, read only
- *   src_cell        device int64 [n_src], flat cell index of each point source
+ *   src_cell        device int64 [n_src], flat cell index of each point source;
+ *                   entries outside the grid are ignored, and reported (EINVAL)
+ *                   only when diag is given (without diag nothing is read back)
  *   src_rate        device double [n_src], photons s^-1; sources sharing a cell add
  *   dt              must satisfy 0 < dt <= dx / (3 c_red) (positivity of the
  *                   unsplit 3D update); larger dt returns EINVAL
@@ -189,7 +191,11 @@ int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double 
  *                   precision): on entry dL/d(state at segment end), on exit
  *                   dL/d(state at segment start)
  *   g_nH            device double [cells], dL/dn_H is ADDED to it
- *   g_src_rate      device double [n_src], dL/d(src_rate) is ADDED to it
+ *   g_src_rate      device double [n_src], dL/d(src_rate) is ADDED to it (nothing
+ *                   for a source whose cell is outside the grid: such sources are
+ *                   ignored by the forward step, and this call does not report them)
+ * The floor N >= 0 and the limiter |F| <= c_red N are reversed along the
+ * decisions the forward took, with the forward's own arithmetic.
  * The segment is recomputed forward from (N0, F0, x0, T0) into the context's
  * tape.  Every boundary kind is differentiated (an inflow face's beam is a
  * constant); the HLL flux is not (EINVAL).  Returns OK, EINVAL or EHIP. */

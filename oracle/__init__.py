@@ -26,6 +26,13 @@ COUNTER_NAMES = ("limiter", "neg_clamp", "x_clamp", "cap_hits",
                  "substeps", "attempts", "max_sub")
 
 
+def use_library(path):
+    """Load the oracle from another build of the same source (the
+    benchmark's -O3 timing build); call before anything else."""
+    global _LIB_PATH, _lib
+    _LIB_PATH, _lib = path, None
+
+
 def lib():
     global _lib
     if _lib is None:

@@ -1,8 +1,13 @@
 """Build the oracle's shared library (test infrastructure only).
 
-One build: ``g++ -O2 -ffp-contract=off`` so that no multiply-add is fused
-behind the reader's back; the same library is what the CPU-baseline timing
-runs, untuned.
+``build()``: the parity build, ``g++ -O2 -ffp-contract=off`` so that no
+multiply-add is fused behind the reader's back; the tests, the smoke check and
+the CPU-baseline leg of the benchmark load it.
+
+``build_timing(path)``: the same source, untouched, compiled
+``-O3 -march=native`` for the host it runs on; the benchmark times it next to
+the parity build (compiler flags alone move a serial CPU code by several
+times, as the paper's gcc/icc comparison shows), and never uses it for parity.
 """
 import os
 import subprocess
@@ -19,6 +24,16 @@ def build(verbose=False):
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     return LIB
+
+
+def build_timing(path, verbose=False):
+    """Timing-only build for the machine that runs it (not portable: build it
+    where it runs)."""
+    cmd = ["g++", "-std=c++17", "-O3", "-march=native", "-fPIC", "-shared", "-o", path, SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return path
 
 
 if __name__ == "__main__":

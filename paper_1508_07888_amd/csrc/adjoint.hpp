@@ -414,34 +414,22 @@ __host__ __device__ inline bool chem_cell_adj1(const GroupConsts &gc, const Chem
     return true;
 }
 
-// Floor and limiter after the stencil: N* = max(N~, 0); F* = F~ c N*/|F~|
-// when |F~| > c N*.  Forward in place (a = the post values).
-__host__ __device__ __forceinline__ bool floor_limit(double &n, double &fx, double &fy, double &fz, double c, bool &floored) {
-    floored = n < 0.0;
-    if (floored) n = 0.0;
-    const double F2 = fx * fx + fy * fy + fz * fz;
-    const double cn = c * n;
-    if (F2 > cn * cn) {
-        const double s = cn / sqrt(F2);
-        fx *= s; fy *= s; fz *= s;
-        return true;
-    }
-    return false;
-}
-
-// Reverse of floor_limit given the PRE values (n, f) and dL/d(post values).
-__host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, double fy, double fz, double c, double &an,
-                                                double &afx, double &afy, double &afz) {
-    const bool floored = n < 0.0;
+// Reverse of the floor and limiter (floor_limit_fwd) along the branch the
+// forward took (taken: bit 0 floored, bit 1 limited), given the PRE values
+// (n, f) and dL/d(post values): N* = max(N~, 0); F* = F~ c N*/|F~| when
+// limited.  The branch is the forward's own decision, never re-decided here.
+__host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, double fy, double fz, double c,
+                                                         int taken, double &an, double &afx, double &afy,
+                                                         double &afz) {
+    const bool floored = (taken & 1) != 0;
     const double np = floored ? 0.0 : n;
-    const double F2 = fx * fx + fy * fy + fz * fz;
-    const double cn = c * np;
-    if (F2 > cn * cn) {
+    if (taken & 2) {
+        const double F2 = fx * fx + fy * fy + fz * fz;
         const double Fn = sqrt(F2);
         const double ux = fx / Fn, uy = fy / Fn, uz = fz / Fn;
         const double ud = ux * afx + uy * afy + uz * afz;
         an += c * ud;
-        const double s = cn / Fn;
+        const double s = c * np / Fn;
         afx = s * (afx - ux * ud);
         afy = s * (afy - uy * ud);
         afz = s * (afz - uz * ud);
@@ -468,17 +456,21 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
                                      int budget) {
     const double c = cp.c;
     double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], aNo[G], aFo[G][3], Sc[G];
+    int taken[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        Npre[g] = (double)Ut[(int64_t)g * V + i];
+        // the forward's floor and limiter, in its own precision and arithmetic
+        S n = Ut[(int64_t)g * V + i];
+        S f[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Fpre[g][k] = (double)Ft[((int64_t)g * 3 + k) * V + i];
-        Nst[g] = Npre[g];
-        Fst[g][0] = Fpre[g][0];
-        Fst[g][1] = Fpre[g][1];
-        Fst[g][2] = Fpre[g][2];
-        bool fl;
-        floor_limit(Nst[g], Fst[g][0], Fst[g][1], Fst[g][2], c, fl);
+        for (int k = 0; k < 3; ++k) f[k] = Ft[((int64_t)g * 3 + k) * V + i];
+        Npre[g] = (double)n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fpre[g][k] = (double)f[k];
+        taken[g] = floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)c);
+        Nst[g] = (double)n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fst[g][k] = (double)f[k];
         aNo[g] = (double)gN[(int64_t)g * V + i];
 #pragma unroll
         for (int k = 0; k < 3; ++k) aFo[g][k] = (double)gF[((int64_t)g * 3 + k) * V + i];
@@ -495,7 +487,8 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     if (deferred) return false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, aN[g], aF[g][0], aF[g][1], aF[g][2]);
+        floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, taken[g], aN[g], aF[g][0], aF[g][1],
+                        aF[g][2]);
         gU[(int64_t)(4 * g) * V + i] = aN[g];
         gU[(int64_t)(4 * g + 1) * V + i] = aF[g][0];
         gU[(int64_t)(4 * g + 2) * V + i] = aF[g][1];

@@ -141,7 +141,8 @@ template <typename S> static Bounds<S> make_bounds(const emma_rt_config &cfg) {
 static const char *config_error(const emma_rt_config *cfg) {
     if (!cfg) return "config is NULL";
     if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return "grid dimensions must be >= 1";
-    if ((int64_t)cfg->nx * cfg->ny * cfg->nz > ((int64_t)1 << 34)) return "grid too large";
+    // the chemistry work list holds 32-bit cell indices
+    if ((int64_t)cfg->nx * cfg->ny * cfg->nz >= ((int64_t)1 << 32)) return "grid too large (at most 2^32 - 1 cells)";
     if (cfg->n_groups < 1 || cfg->n_groups > EMMA_RT_MAX_GROUPS) return "n_groups must be in 1..4";
     if (!(cfg->dx > 0) || !isfinite(cfg->dx)) return "dx must be > 0";
     if (!(cfg->c_red > 0) || cfg->c_red > kC * (1 + 1e-12)) return "c_red must be in (0, c]";

@@ -335,13 +335,10 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
             R fx = cur.fx + lam * ((fxl.fx - fxr.fx) + (fyl.fx - fyr.fx) + (flo.fx - fup.fx));
             R fy = cur.fy + lam * ((fxl.fy - fxr.fy) + (fyl.fy - fyr.fy) + (flo.fy - fup.fy));
             R fz = cur.fz + lam * ((fxl.fz - fxr.fz) + (fyl.fz - fyr.fz) + (flo.fz - fup.fz));
-            if (n < R(0)) { n = R(0); if (active) nneg++; }
-            const R F2 = fx * fx + fy * fy + fz * fz;
-            const R cn = c * n;
-            if (F2 > cn * cn) {
-                const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
-                fx *= sc; fy *= sc; fz *= sc;
-                if (active) nlim++;
+            const int taken = floor_limit_fwd(n, fx, fy, fz, c);
+            if (active) {
+                nneg += taken & 1;
+                nlim += taken >> 1;
             }
             us = Vec4<R>{n, fx, fy, fz};
         }
@@ -564,13 +561,10 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
                 R fy = cur[g].fy + hl * ((aL.fy + bR.fy) + (aD.fy + bT.fy) + (Az2[g].fy + Bz2[g].fy) - s6 * cur[g].fy);
                 R fz = cur[g].fz + hl * ((aL.fz + bR.fz) + (aD.fz + bT.fz) + (Az2[g].fz + Bz2[g].fz) - s6 * cur[g].fz);
                 if (!a.nolimit) {
-                    if (n < R(0)) { n = R(0); if (active) nneg++; }
-                    const R F2 = fx * fx + fy * fy + fz * fz;
-                    const R cn = c * n;
-                    if (F2 > cn * cn) {
-                        const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
-                        fx *= sc; fy *= sc; fz *= sc;
-                        if (active) nlim++;
+                    const int taken = floor_limit_fwd(n, fx, fy, fz, c);
+                    if (active) {
+                        nneg += taken & 1;
+                        nlim += taken >> 1;
                     }
                 }
                 us[g] = Vec4<R>{n, fx, fy, fz};

@@ -352,15 +352,10 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
             }
             R n = Ni + lam * acc[0];
             R f[3] = {Fi[0] + lam * acc[1], Fi[1] + lam * acc[2], Fi[2] + lam * acc[3]};
-            if (!NOLIMIT && n < R(0)) { n = R(0); nneg++; }
-            const R F2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
-            if (!NOLIMIT && F2 > R(0)) {
-                const R Fn = FastMath<R>::sqrt(F2);
-                if (Fn > c * n) {
-                    const R s = FastMath<R>::div(c * n, Fn);
-                    f[0] *= s; f[1] *= s; f[2] *= s;
-                    nlim++;
-                }
+            if (!NOLIMIT) {
+                const int taken = floor_limit_fwd(n, f[0], f[1], f[2], c);
+                nneg += taken & 1;
+                nlim += taken >> 1;
             }
             Ns[(int64_t)g * V + i] = n;
             Fs[(int64_t)g * 3 * V + i] = f[0];

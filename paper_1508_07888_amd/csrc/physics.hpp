@@ -94,6 +94,31 @@ __device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) 
     P[5] = a + k * gz * gz;
 }
 
+// The floor N* >= 0 and the limiter |F*| <= c N* after the transport update
+// (reading R13), in the transport's own precision R.  Every forward kernel
+// and the adjoint's replay of the forward call this one function, so the
+// adjoint reverses the branch the forward took (bit 0: floored, bit 1:
+// limited) and continues from the forward's own post-limiter values.
+template <typename R>
+__device__ __forceinline__ int floor_limit_fwd(R &n, R &fx, R &fy, R &fz, R c) {
+#pragma clang fp contract(off)
+    int taken = 0;
+    if (n < R(0)) {
+        n = R(0);
+        taken = 1;
+    }
+    const R F2 = fx * fx + fy * fy + fz * fz;
+    const R cn = c * n;
+    if (F2 > cn * cn) {
+        const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
+        fx *= sc;
+        fy *= sc;
+        fz *= sc;
+        taken |= 2;
+    }
+    return taken;
+}
+
 // Signal speeds along one axis for the HLL flux: the eigenvalues of the
 // one-dimensional M1 system (N, F_d) -> (F_d, c^2 chi(f) N) at the normal
 // reduced flux f = F_d/(c N) in [-1, 1] (0 when N <= 0),

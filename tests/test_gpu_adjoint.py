@@ -75,6 +75,68 @@ def test_adjoint_dot_product_against_oracle_tangent(shape, G, seed, steps, otsa)
     rt.close()
 
 
+@pytest.mark.parametrize("shape,G,seed,steps", [((9, 8, 10), 2, 11, 1), ((7, 12, 66), 3, 12, 1)])
+def test_adjoint_dot_product_through_floor_limiter_and_clip(shape, G, seed, steps):
+    """Inputs that make the floor, the limiter and the closure clip fire by a
+    margin (no decision near its threshold, so the oracle's tangent and the
+    library's forward take the same branches): 15 % of the cells with
+    |F| = (1.05..1.5) c N (unrealisable: clipped closure, limited after the
+    update), 5 % dark (N = F = 0), 5 % with N < 0 (floored).  The reverse of
+    the floor and the limiter follows the forward's own decisions.  One step:
+    a limited cell leaves the step at f = 1 to rounding, where the next step's
+    closure sits on its kink and the two implementations may legitimately
+    take different sides."""
+    c = 0.1 * E.C_LIGHT
+    dx = 6.6 * E.KPC / 32
+    dt = E.courant_dt(dx, c)
+    N, F, x, T, n0 = E.random_state(shape, G, c, seed=seed, n_scale=1e-2, f_max=0.6, p_full=0.0,
+                                    p_dark=0.0)
+    rng = np.random.default_rng(seed)
+    hi = rng.random(N.shape) < 0.15
+    F[:, :, :, :, :] = np.where(hi[:, None], F / np.maximum(np.linalg.norm(F, axis=1, keepdims=True), 1e-300)
+                                * c * N[:, None] * rng.uniform(1.05, 1.5, N.shape)[:, None], F)
+    dark = (rng.random(N.shape) < 0.05) & ~hi
+    N[dark] = 0.0
+    F[np.broadcast_to(dark[:, None], F.shape)] = 0.0
+    neg = (rng.random(N.shape) < 0.05) & ~hi & ~dark
+    N[neg] = -0.3 * N[neg]
+    V = int(np.prod(shape))
+    cells = rng.integers(0, V, 4).astype(np.int64)
+    rates = 10 ** rng.uniform(48, 50, 4)
+    g = groups_for(G)
+    dN = N * rng.standard_normal(N.shape)
+    dF = F * rng.standard_normal(F.shape)
+    dxh = x * (1 - x) * rng.standard_normal(x.shape)
+    dT = T * rng.standard_normal(T.shape)
+    dn0 = n0 * rng.standard_normal(n0.shape)
+    dr = rates * rng.standard_normal(rates.shape)
+    kw = dict(dx=dx, c_red=c, dt=dt, n_steps=steps, groups=g)
+    (oN, oF, ox, oT), (tN, tF, tx, tT), cnt = oracle.run_tangent(
+        N, F, x, T, n0, cells, rates, dN, dF, dxh, dT, dn0, dr, **kw)
+    assert cnt["limiter"] > 0 and cnt["neg_clamp"] > 0, cnt
+    wN = rng.standard_normal(N.shape) / (np.abs(oN).max() + 1e-300)
+    wF = rng.standard_normal(F.shape) / (np.abs(oF).max() + 1e-300)
+    wx = rng.standard_normal(x.shape)
+    wT = rng.standard_normal(T.shape) / np.abs(oT).max()
+    lhs = (wN * tN).sum() + (wF * tF).sum() + (wx * tx).sum() + (wT * tT).sum()
+    rt = _rt(shape, G, dx, c, steps)
+    gN, gF, gx, gT = to_dev(wN), to_dev(wF), to_dev(wx), to_dev(wT)
+    g_n0 = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    g_rate = torch.zeros(4, dtype=torch.float64, device=DEV)
+    rt.step_adjoint(to_dev(N), to_dev(F), to_dev(x), to_dev(T), to_dev(n0), to_dev(cells, torch.int64),
+                    to_dev(rates), dt, steps, gN, gF, gx, gT, g_n0, g_rate)
+    torch.cuda.synchronize()
+    parts = [(gN.cpu().numpy() * dN).sum(), (gF.cpu().numpy() * dF).sum(),
+             (gx.cpu().numpy() * dxh).sum(), (gT.cpu().numpy() * dT).sum(),
+             (g_n0.cpu().numpy() * dn0).sum(), (g_rate.cpu().numpy() * dr).sum()]
+    rhs = sum(parts)
+    scale = sum(abs(p) for p in parts)
+    print(f"{shape} G={G} limiter {cnt['limiter']} floor {cnt['neg_clamp']}: <w,Jv> {lhs:.14e} "
+          f"<J^T w,v> {rhs:.14e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-9 * max(scale, abs(lhs))
+    rt.close()
+
+
 def _loss_setup(precision="fp64"):
     w = E.make_workload("adjoint64")
     G, shape = w["G"], w["shape"]
@@ -125,8 +187,17 @@ def test_adjoint64_gradient_matches_central_differences():
     assert stable >= 6
     rng = np.random.default_rng(0)
     n_stable = 0
-    for trial in range(3):
-        dn = st["n0"] * torch.tensor(rng.standard_normal(w["shape"]), device=DEV)
+    # n0 directions: three over the whole grid, then five supported on 4^3
+    # blocks inside the loss volume (fewer cells whose chemistry decisions a
+    # perturbation can flip); at least two must be decision-stable
+    for trial in range(8):
+        d = rng.standard_normal(w["shape"])
+        if trial >= 3:
+            m = np.zeros(w["shape"])
+            z, y, x = rng.integers(24, 36, 3)
+            m[z:z + 4, y:y + 4, x:x + 4] = 1.0
+            d *= m
+        dn = st["n0"] * torch.tensor(d, device=DEV)
         lp, dp = _forward_loss(w, rt, st, sub, st["n0"] + h * dn, st["rates"], diag=True)
         lm, dm = _forward_loss(w, rt, st, sub, st["n0"] - h * dn, st["rates"], diag=True)
         fd = (lp - lm) / (2 * h)
@@ -138,6 +209,7 @@ def test_adjoint64_gradient_matches_central_differences():
         if same:
             n_stable += 1
             assert rel <= 1e-5
+    assert n_stable >= 2
     rt.close()
 
 

@@ -164,10 +164,13 @@ def test_large512_forward_and_adjoint():
     # adjoint of K steps from the initial state (the tape holds all K states):
     # loss = sum of x_HII at a few cells far apart; for each cell, the gradient
     # contracted with a direction supported on the block around it must equal
-    # the oracle's dual-number tangent of that cell's x on the block
+    # the oracle's dual-number tangent of that cell's x on the block.  Both
+    # precisions run the same adjoint: the FP64 path is the derivative of the
+    # FP64 step and agrees with the oracle's tangent to 1e-9; the mixed path is
+    # the derivative of the FP32-transport step (its state differs from the
+    # FP64 one by FP32 rounding, ~1e-7 relative per step, and the chemistry
+    # amplifies that in the heated cells next to the sources), held to 1e-3.
     shape, G = w["shape"], w["G"]
-    rt = EmmaRT(shape, G, w["dx"], w["c_red"], precision="mixed", T_bb=w["T_bb"],
-                edges_eV=w["edges"], adjoint_max_steps=K, device=DEV)
     r = K + 1
     src = np.unique(w["src_cell"])
     chosen = []
@@ -179,25 +182,29 @@ def test_large512_forward_and_adjoint():
             chosen.append(c)
         if len(chosen) == 4:
             break
-    fdt = rt.dtype
-    N0, F0 = to_dev(w["N"], fdt), to_dev(w["F"], fdt)
-    x0, T0, n0 = to_dev(w["x"]), to_dev(w["T"]), to_dev(w["n0"])
-    cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
-    gN, gF = torch.zeros_like(N0), torch.zeros_like(F0)
-    gx, gT = torch.zeros_like(x0), torch.zeros_like(T0)
-    g_n0 = torch.zeros_like(n0)
-    g_rate = torch.zeros_like(rates)
-    for c in chosen:
-        gx[tuple(int(v) for v in c)] = 1.0
-    rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
-    torch.cuda.synchronize()
-    rt.close()
+    assert len(chosen) == 4
+    grads = {}
+    for precision in ("mixed", "fp64"):
+        rt = EmmaRT(shape, G, w["dx"], w["c_red"], precision=precision, T_bb=w["T_bb"],
+                    edges_eV=w["edges"], adjoint_max_steps=K, device=DEV)
+        fdt = rt.dtype
+        N0, F0 = to_dev(w["N"], fdt), to_dev(w["F"], fdt)
+        x0, T0, n0 = to_dev(w["x"]), to_dev(w["T"]), to_dev(w["n0"])
+        cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
+        gN, gF = torch.zeros_like(N0), torch.zeros_like(F0)
+        gx, gT = torch.zeros_like(x0), torch.zeros_like(T0)
+        g_n0 = torch.zeros_like(n0)
+        g_rate = torch.zeros_like(rates)
+        for c in chosen:
+            gx[tuple(int(v) for v in c)] = 1.0
+        rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+        torch.cuda.synchronize()
+        rt.close()
+        grads[precision] = (gN.double().cpu().numpy(), gx.cpu().numpy(), gT.cpu().numpy(), g_n0.cpu().numpy())
+        del gN, gF, gx, gT, g_n0, N0, F0, x0, T0, n0
+        torch.cuda.empty_cache()
     g = groups_for(G)
     rng = np.random.default_rng(7)
-    hN, hx, hT, hn0 = gN.cpu().numpy(), gx.cpu().numpy(), gT.cpu().numpy(), g_n0.cpu().numpy()
-    del gN, gF, gx, gT, g_n0, N0, F0, x0, T0, n0
-    torch.cuda.empty_cache()
-    assert len(chosen) == 4
     for c in chosen:
         cz, cy, cx = (int(v) for v in c)
         bN, bF, bx, bT, bn0, bc, br = _block(w, (cz, cy, cx), r)
@@ -213,10 +220,13 @@ def test_large512_forward_and_adjoint():
         lhs = float(tx[r, r, r])
         idx = [np.arange(v - r, v + r + 1) % n for v, n in zip((cz, cy, cx), shape)]
         sel = np.ix_(*idx)
-        parts = [float((hN[(slice(None),) + sel].astype(np.float64) * dN).sum()),
-                 float((hx[sel] * dxh).sum()), float((hT[sel] * dT).sum()),
-                 float((hn0[sel] * dn0).sum())]
-        rhs = sum(parts)
-        scale = sum(abs(p) for p in parts)
-        print(f"cell {cz, cy, cx}: tangent {lhs:.10e} adjoint {rhs:.10e} parts {parts}", flush=True)
-        assert abs(lhs - rhs) <= 1e-3 * max(scale, abs(lhs))
+        for precision, tol in (("fp64", 1e-9), ("mixed", 1e-3)):
+            hN, hx, hT, hn0 = grads[precision]
+            parts = [float((hN[(slice(None),) + sel] * dN).sum()), float((hx[sel] * dxh).sum()),
+                     float((hT[sel] * dT).sum()), float((hn0[sel] * dn0).sum())]
+            rhs = sum(parts)
+            scale = sum(abs(p) for p in parts)
+            err = abs(lhs - rhs) / max(scale, abs(lhs))
+            print(f"cell {cz, cy, cx} {precision}: tangent {lhs:.12e} adjoint {rhs:.12e} rel {err:.2e}",
+                  flush=True)
+            assert err <= tol
