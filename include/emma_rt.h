@@ -154,6 +154,33 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
                  const double *n_H, const int64_t *src_cell, const double *src_rate,
                  int32_t n_src, double dt, int32_t n_steps, emma_rt_diag *diag);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): emma_rt_step
+ * without a context.  The scratch a context would own (transport output or
+ * ping-pong fields, source table, counters, chemistry work list) lives in one
+ * fixed device array of EMMA_RT_NOALLOC_SCRATCH_BYTES compiled into the
+ * library; every GPU the library runs on holds its own copy until the process
+ * ends.  Nothing is allocated: no hipMalloc, hipFree or allocating library call.
+ *   cfg             as for emma_rt_init (read here, not kept); adjoint_max_steps
+ *                   is ignored
+ *   hip_stream      hipStream_t of the call (NULL = the default stream)
+ *   N ... n_steps   as emma_rt_step (no diagnostics: src_cell entries outside
+ *                   the grid are ignored without a report)
+ * Scratch needed, each piece rounded up to 256 bytes: 4 G V e (N and F; e = 4
+ * mixed, 8 FP64) + 4 V (work list) + V/8 (source mask) + 12 n_src + 8 G n_src
+ * (source table) + 14336 (counters) + 64.  A grid and source list needing more
+ * than EMMA_RT_NOALLOC_SCRATCH_BYTES return EINVAL before anything runs (a
+ * 128^3 grid with 3 groups in mixed precision fits; in FP64 it does not).
+ * All calls on one GPU share that GPU's array and the next call overwrites it:
+ * calls that overlap on one GPU (two streams, two host threads) race and must
+ * be serialised by the caller.  Errors are reported through
+ * emma_rt_last_error(NULL) (one message per process, not per thread).
+ * Returns OK, EINVAL or EHIP. */
+#define EMMA_RT_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int emma_rt_step_noalloc(const emma_rt_config *cfg, void *hip_stream, void *N, void *F,
+                         double *x_HII, double *T, const double *n_H, const int64_t *src_cell,
+                         const double *src_rate, int32_t n_src, double dt, int32_t n_steps);
+
 /* emma_rt_step with static refinement: the coarse radiative transport
  * approximation of Sec. 5.  The transport runs on the coarse grid only; each
  * refined coarse cell has r^3 children (r = ratio, 2 or 4) with their own gas,

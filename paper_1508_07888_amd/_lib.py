@@ -29,7 +29,8 @@ FLUXES = {"glf": 0, "hll": 1}
 
 EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_crta", "emma_rt_step_adjoint", "emma_rt_free",
            "emma_rt_last_error", "emma_rt_group_constants", "emma_rt_scratch_bytes",
-           "emma_rt_profile_enable", "emma_rt_profile_read")
+           "emma_rt_profile_enable", "emma_rt_profile_read", "emma_rt_step_noalloc")
+NOALLOC_SCRATCH_BYTES = 128 << 20  # EMMA_RT_NOALLOC_SCRATCH_BYTES
 
 
 class emma_rt_config(ctypes.Structure):
@@ -110,6 +111,9 @@ def load():
     L.emma_rt_profile_read.restype = ctypes.c_int
     L.emma_rt_profile_read.argtypes = [_vp, ctypes.POINTER(emma_rt_kernel_time), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]
+    L.emma_rt_step_noalloc.restype = ctypes.c_int
+    L.emma_rt_step_noalloc.argtypes = [ctypes.POINTER(emma_rt_config), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32]
     L.emma_rt_scratch_bytes.restype = ctypes.c_int64
     L.emma_rt_scratch_bytes.argtypes = [ctypes.POINTER(emma_rt_config)]
     _lib = L
@@ -160,6 +164,14 @@ def emma_rt_step(ctx, N, F, x, T, n0, src_cell, src_rate, n_src, dt, n_steps, di
     return L.emma_rt_step(ctx, _vp(N), _vp(F), _vp(x), _vp(T), _vp(n0), _vp(src_cell),
                           _vp(src_rate), int(n_src), float(dt), int(n_steps),
                           ctypes.byref(diag) if diag is not None else None)
+
+
+def emma_rt_step_noalloc(cfg, stream_ptr, N, F, x, T, n0, src_cell, src_rate, n_src, dt, n_steps):
+    """emma_rt_step without a context or any allocation (fixed library scratch);
+    pointers are integers (device addresses); returns the status code."""
+    L = load()
+    return L.emma_rt_step_noalloc(ctypes.byref(cfg), _vp(stream_ptr), _vp(N), _vp(F), _vp(x), _vp(T), _vp(n0),
+                                  _vp(src_cell), _vp(src_rate), int(n_src), float(dt), int(n_steps))
 
 
 def emma_rt_step_adjoint(ctx, N0, F0, x0, T0, n0, src_cell, src_rate, n_src, dt, n_steps,

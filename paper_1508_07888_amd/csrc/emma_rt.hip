@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -480,10 +481,10 @@ static int step_typed(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
     return EMMA_RT_OK;
 }
 
-extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double *T, const double *n0,
-                            const int64_t *cell, const double *rate, int32_t n_src, double dt,
-                            int32_t n_steps, emma_rt_diag *d) {
-    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+// Checks shared by emma_rt_step and emma_rt_step_noalloc (c holds the config).
+static int step_args(emma_rt_ctx *c, const void *N, const void *F, const double *x, const double *T,
+                     const double *n0, const int64_t *cell, const double *rate, int32_t n_src, double dt,
+                     int32_t n_steps) {
     if (!N || !F || !x || !T || !n0) return fail(c, EMMA_RT_EINVAL, "a field pointer is NULL");
     if (n_src < 0 || n_src > EMMA_RT_MAX_SOURCES)
         return fail(c, EMMA_RT_EINVAL, "n_src must be in 0..%d", EMMA_RT_MAX_SOURCES);
@@ -492,10 +493,12 @@ extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double 
     if (!(dt > 0) || !isfinite(dt)) return fail(c, EMMA_RT_EINVAL, "dt must be > 0");
     if (dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
         return fail(c, EMMA_RT_EINVAL, "dt = %g exceeds dx/(3 c_red) = %g", dt, c->cfg.dx / (3.0 * c->cfg.c_red));
-    int dev = -1;
-    (void)hipGetDevice(&dev);
-    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
-    c->err[0] = 0;
+    return EMMA_RT_OK;
+}
+
+static int step_dispatch(emma_rt_ctx *c, void *N, void *F, double *x, double *T, const double *n0,
+                         const int64_t *cell, const double *rate, int32_t n_src, double dt, int32_t n_steps,
+                         emma_rt_diag *d) {
     const int G = c->cfg.n_groups;
     const bool f64 = c->cfg.precision == EMMA_RT_FP64;
 #define DISPATCH(GG)                                                                                      \
@@ -512,6 +515,117 @@ extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double 
     }
 #undef DISPATCH
     return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
+}
+
+extern "C" int emma_rt_step(emma_rt_ctx *c, void *N, void *F, double *x, double *T, const double *n0,
+                            const int64_t *cell, const double *rate, int32_t n_src, double dt,
+                            int32_t n_steps, emma_rt_diag *d) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (int e = step_args(c, N, F, x, T, n0, cell, rate, n_src, dt, n_steps)) return e;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
+    c->err[0] = 0;
+    return step_dispatch(c, N, F, x, T, n0, cell, rate, n_src, dt, n_steps, d);
+}
+
+// ------------------------------------------- allocation-free step variant
+// emma_rt_step for callers that cannot allocate device memory: the scratch a
+// context would own (transport output / ping-pong fields, source table,
+// counters, chemistry work list) is carved out of this fixed array instead.
+// In host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, taken once per device on the first call there.
+static __device__ __align__(256) unsigned char scratch[EMMA_RT_NOALLOC_SCRATCH_BYTES];
+
+static const int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's copy of `scratch` (nullptr on failure,
+// with the reason in g_static_err).
+static void *scratch_on(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            fail(nullptr, EMMA_RT_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                 hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Places the step's scratch at 256-byte aligned offsets from base (which may
+// be null to measure); returns the bytes used.
+static int64_t noalloc_layout(emma_rt_ctx *c, unsigned char *base, int n_src) {
+    const int64_t V = c->grid.V;
+    const int G = c->cfg.n_groups;
+    int64_t off = 0;
+    auto take = [&](int64_t n) {
+        unsigned char *p = base ? base + off : nullptr;
+        off += (n + 255) / 256 * 256;
+        return (void *)p;
+    };
+    c->Ns = take((int64_t)G * V * (int64_t)c->elem);
+    c->Fs = take((int64_t)3 * G * V * (int64_t)c->elem);
+    c->mask = (uint32_t *)take(c->mask_words * 4);
+    c->sorted_cell = (int64_t *)take((int64_t)n_src * 8);
+    c->sorted_idx = (int32_t *)take((int64_t)n_src * 4);
+    c->S = (double *)take((int64_t)n_src * G * 8);
+    c->cnt = (unsigned long long *)take((int64_t)kCntSlots * CNT_COUNT * 8);
+    c->work_count = (uint32_t *)take(64);
+    c->work_cells = (uint32_t *)take(V * 4);
+    return off;
+}
+
+extern "C" int emma_rt_step_noalloc(const emma_rt_config *cfg, void *stream, void *N, void *F, double *x,
+                                    double *T, const double *n0, const int64_t *cell, const double *rate,
+                                    int32_t n_src, double dt, int32_t n_steps) {
+    if (const char *why = config_error(cfg)) return fail(nullptr, EMMA_RT_EINVAL, "%s", why);
+    // a context on the stack: host memory only, its device pointers set below
+    emma_rt_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.cfg = *cfg;
+    c.stream = (hipStream_t)stream;
+    c.grid = Grid{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz};
+    c.elem = cfg->precision == EMMA_RT_FP64 ? 8 : 4;
+    c.bnd_f = make_bounds<float>(*cfg);
+    c.bnd_d = make_bounds<double>(*cfg);
+    c.mask_words = (c.grid.V + 31) / 32;
+    int rc = step_args(&c, N, F, x, T, n0, cell, rate, n_src, dt, n_steps);
+    if (rc == EMMA_RT_OK) {
+        const int64_t need = noalloc_layout(&c, nullptr, n_src);
+        if (need > (int64_t)EMMA_RT_NOALLOC_SCRATCH_BYTES)
+            rc = fail(&c, EMMA_RT_EINVAL,
+                      "grid and sources need %lld bytes of scratch, above the fixed %lld of "
+                      "emma_rt_step_noalloc: use emma_rt_init / emma_rt_step",
+                      (long long)need, (long long)EMMA_RT_NOALLOC_SCRATCH_BYTES);
+    }
+    if (rc == EMMA_RT_OK) {
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+            return fail(nullptr, EMMA_RT_EHIP, "no usable current HIP device");
+        c.device = dev;
+        void *base = scratch_on(dev);
+        if (!base) return EMMA_RT_EHIP;
+        noalloc_layout(&c, (unsigned char *)base, n_src);
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        const int64_t blocks = (c.grid.V + 255) / 256;
+        c.list_blocks = (int)((int64_t)cus * 8 < blocks ? (int64_t)cus * 8 : blocks);
+        // the counters take atomic adds (bad source cells) and must start at zero
+        hipLaunchKernelGGL(k_fill_u64, dim3((kCntSlots * CNT_COUNT + 255) / 256), dim3(256), 0, c.stream, c.cnt,
+                           (int)(kCntSlots * CNT_COUNT), 0ull);
+        rc = check_launch(&c, "k_fill_u64");
+        if (rc == EMMA_RT_OK) rc = step_dispatch(&c, N, F, x, T, n0, cell, rate, n_src, dt, n_steps, nullptr);
+    }
+    if (rc != EMMA_RT_OK) memcpy(g_static_err, c.err, sizeof(g_static_err));
+    else g_static_err[0] = 0;
+    return rc;
 }
 
 // ------------------------------------------------- refined cells (Sec. 5)

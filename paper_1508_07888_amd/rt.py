@@ -160,6 +160,18 @@ class EmmaRT:
             return out
         return rc
 
+    def step_noalloc(self, N, F, x, T, n0, src_cell, src_rate, dt, n_steps=1, raise_on_status=True):
+        """The same steps through emma_rt_step_noalloc: this context's
+        configuration and stream, the library's fixed scratch instead of the
+        context's (no device allocation in the call; no diagnostics)."""
+        pN, pF, px, pT, pn = self._fields(N, F, x, T, n0)
+        n, pc, pr = self._sources(src_cell, src_rate)
+        rc = _lib.emma_rt_step_noalloc(self.cfg, self.stream.cuda_stream, pN, pF, px, pT, pn, pc, pr, n, dt,
+                                       n_steps)
+        if rc != _lib.EMMA_RT_OK and raise_on_status:
+            raise _lib.EmmaError(rc, _lib.emma_rt_last_error(None))
+        return rc
+
     def step_crta(self, N, F, x, T, n0, src_cell, src_rate, dt, ref_cell, ratio, x_fine, T_fine, n_fine,
                   n_steps=1, src_child=None, diag=False, raise_on_status=True):
         """Steps with static refinement (coarse transport, chemistry on the

@@ -115,3 +115,24 @@ def test_group_constants_reject_bad_edges():
         _lib.emma_rt_group_constants(1e5, [13.6, 10.0])
     with pytest.raises(_lib.EmmaError):
         _lib.emma_rt_group_constants(1e5, [13.6, 20, 30, 40, 50, 60])
+
+
+def test_noalloc_rejects_before_touching_the_gpu():
+    """The allocation-free step checks its arguments and its fixed scratch
+    size on the host, before any HIP call (fake device addresses are never
+    dereferenced)."""
+    p = [0x1000] * 5
+    big = _cfg(nx=160, ny=160, nz=160, n_groups=3, precision=_lib.EMMA_RT_MIXED)
+    dt = big.dx / (3 * big.c_red)
+    rc = _lib.emma_rt_step_noalloc(big, 0, *p, 0, 0, 0, dt, 1)
+    assert rc == _lib.EMMA_RT_EINVAL
+    assert "scratch" in _lib.emma_rt_last_error(None)
+    assert _lib.emma_rt_step_noalloc(_cfg(nx=0), 0, *p, 0, 0, 0, 1.0, 1) == _lib.EMMA_RT_EINVAL
+    assert "grid" in _lib.emma_rt_last_error(None)
+    small = _cfg()
+    assert _lib.emma_rt_step_noalloc(small, 0, *p, 0, 0, 0, small.dx / small.c_red, 1) == _lib.EMMA_RT_EINVAL
+    assert "exceeds" in _lib.emma_rt_last_error(None)
+    assert _lib.emma_rt_step_noalloc(small, 0, 0, *p[1:], 0, 0, 0, 1.0, 1) == _lib.EMMA_RT_EINVAL
+    # the largest 3-group mixed grid the header promises fits: 128^3 (argument
+    # checks pass, so only the missing GPU stops the call here)
+    assert 4 * 3 * 128 ** 3 * 4 + 4 * 128 ** 3 + 128 ** 3 // 8 + 14336 + 4 * 256 < _lib.NOALLOC_SCRATCH_BYTES
