@@ -97,34 +97,26 @@ __device__ __forceinline__ Vec4<R> ghost4(const Bounds<R> &b, int face, int g, R
     return Vec4<R>{u.n, f[0], f[1], f[2]};
 }
 
-// The four x/y split vectors (times 2) of one state with its closure.
-// The transport arithmetic here, in az2/bz2, in the closure and in the update
-// is kept free of FMA contraction: whether the compiler fuses a product into
-// an add depends on the surrounding code, which differs between the first
-// plane of a z tile and the planes rolled through the window (and between the
-// split and fused kernels), and the result must not depend on the tiling.
+// The four x/y split vectors (times 2) of one state U = (N, F) with its
+// flux-form closure cP = c^2 P: 2 A_d = Ft_d + c U, 2 B_d = c U - Ft_d with
+// Ft_d = (F_d, c^2 P_xd, c^2 P_yd, c^2 P_zd).
 template <typename R>
-__device__ __forceinline__ void split_xy(const Vec4<R> &u, const R P[6], R c, Vec4<R> &Ax, Vec4<R> &Bx,
+__device__ __forceinline__ void split_xy(const Vec4<R> &u, const R cP[6], R c, Vec4<R> &Ax, Vec4<R> &Bx,
                                          Vec4<R> &Ay, Vec4<R> &By) {
-#pragma clang fp contract(off)
-    const R cN = c * u.n, cFx = c * u.fx, cFy = c * u.fy, cFz = c * u.fz, cc = c * c;
-    const R pxx = cc * P[0], pxy = cc * P[1], pxz = cc * P[2], pyy = cc * P[3], pyz = cc * P[4];
-    Ax = Vec4<R>{u.fx + cN, pxx + cFx, pxy + cFy, pxz + cFz};
-    Bx = Vec4<R>{cN - u.fx, cFx - pxx, cFy - pxy, cFz - pxz};
-    Ay = Vec4<R>{u.fy + cN, pxy + cFx, pyy + cFy, pyz + cFz};
-    By = Vec4<R>{cN - u.fy, cFx - pxy, cFy - pyy, cFz - pyz};
+    Ax = Vec4<R>{c * u.n + u.fx, c * u.fx + cP[0], c * u.fy + cP[1], c * u.fz + cP[2]};
+    Bx = Vec4<R>{c * u.n - u.fx, c * u.fx - cP[0], c * u.fy - cP[1], c * u.fz - cP[2]};
+    Ay = Vec4<R>{c * u.n + u.fy, c * u.fx + cP[1], c * u.fy + cP[3], c * u.fz + cP[4]};
+    By = Vec4<R>{c * u.n - u.fy, c * u.fx - cP[1], c * u.fy - cP[3], c * u.fz - cP[4]};
 }
 
-// A_z and B_z parts (times 2) of one state with its closure.
+// A_z and B_z parts (times 2) of one state with its flux-form closure.
 template <typename R>
-__device__ __forceinline__ Vec4<R> az2(const Vec4<R> &u, const R P[6], R c) {
-#pragma clang fp contract(off)
-    return Vec4<R>{u.fz + c * u.n, c * c * P[2] + c * u.fx, c * c * P[4] + c * u.fy, c * c * P[5] + c * u.fz};
+__device__ __forceinline__ Vec4<R> az2(const Vec4<R> &u, const R cP[6], R c) {
+    return Vec4<R>{c * u.n + u.fz, c * u.fx + cP[2], c * u.fy + cP[4], c * u.fz + cP[5]};
 }
 template <typename R>
-__device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R P[6], R c) {
-#pragma clang fp contract(off)
-    return Vec4<R>{c * u.n - u.fz, c * u.fx - c * c * P[2], c * u.fy - c * c * P[4], c * u.fz - c * c * P[5]};
+__device__ __forceinline__ Vec4<R> bz2(const Vec4<R> &u, const R cP[6], R c) {
+    return Vec4<R>{c * u.n - u.fz, c * u.fx - cP[2], c * u.fy - cP[4], c * u.fz - cP[5]};
 }
 
 // ------------------------------------------------------------ HLL, tiled
@@ -147,7 +139,6 @@ __device__ __forceinline__ Speeds2<R> hll_speeds(const Vec4<R> &u, int d, R c) {
 
 template <typename R>
 __device__ __forceinline__ Vec4<R> hll_ft(const Vec4<R> &u, const R P[6], R c, int d) {
-#pragma clang fp contract(off)
     const R cc = c * c;
     const int i0 = d == 0 ? 0 : (d == 1 ? 1 : 2), i1 = d == 0 ? 1 : (d == 1 ? 3 : 4),
               i2 = d == 0 ? 2 : (d == 1 ? 4 : 5);
@@ -158,7 +149,6 @@ __device__ __forceinline__ Vec4<R> hll_ft(const Vec4<R> &u, const R P[6], R c, i
 template <typename R>
 __device__ __forceinline__ Vec4<R> hll_face(const Vec4<R> &uL, const Vec4<R> &fL, Speeds2<R> sL, const Vec4<R> &uR,
                                             const Vec4<R> &fR, Speeds2<R> sR) {
-#pragma clang fp contract(off)
     const R am = sL.lo < sR.lo ? sL.lo : sR.lo;
     const R ap = sL.hi > sR.hi ? sL.hi : sR.hi;
     const R inv = FastMath<R>::rcp(ap - am), pm = ap * am;
@@ -323,7 +313,6 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
         __syncthreads();
         Vec4<R> us;
         {
-#pragma clang fp contract(off)
             const Vec4<R> fxl = hll_face(lU[buf][ty + 1][tx], lFx[buf][ty][tx], lSx[buf][ty][tx], cur, ftx, sx);
             const Vec4<R> fxr =
                 hll_face(cur, ftx, sx, lU[buf][ty + 1][tx + 2], lFx[buf][ty][tx + 2], lSx[buf][ty][tx + 2]);
@@ -447,7 +436,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
     // z faces: ghosts of plane 0 below the grid and of plane nz-1 above it
     const bool zlo_ghost = bd.kind[4] != BC_PERIODIC, zhi_ghost = bd.kind[5] != BC_PERIODIC;
 
-    const R c = a.c, half = R(0.5);
+    const R c = a.c, cc = c * c, half = R(0.5);
     // The z march keeps a window of U = PD + 2 planes of the own column in
     // registers, W[(z - z0) mod U] = plane z, and of the halo column, H[...]:
     // the planes z and z+1 in use and PD planes in flight.  The loop is
@@ -491,10 +480,10 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
             if (z0 == 0 && zlo_ghost) um[g] = ghost4(bd, 4, g, c, W[0][g]);
             if (z0 + 1 == nz && zhi_ghost) W[1][g] = ghost4(bd, 5, g, c, W[0][g]);
             R Pm[6];
-            m1_pressure(um[g].n, um[g].fx, um[g].fy, um[g].fz, c, Pm);
+            m1_pressure(um[g].n, um[g].fx, um[g].fy, um[g].fz, c, Pm, cc);
             Az2[g] = az2(um[g], Pm, c);
-            m1_pressure(W[0][g].n, W[0][g].fx, W[0][g].fy, W[0][g].fz, c, Pc[g]);
-            m1_pressure(W[1][g].n, W[1][g].fx, W[1][g].fy, W[1][g].fz, c, Pn[g]);
+            m1_pressure(W[0][g].n, W[0][g].fx, W[0][g].fy, W[0][g].fz, c, Pc[g], cc);
+            m1_pressure(W[1][g].n, W[1][g].fx, W[1][g].fy, W[1][g].fz, c, Pn[g], cc);
             Bz2[g] = bz2(W[1][g], Pn[g], c);
         }
     }
@@ -512,7 +501,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
             // the fused kernel recomputes plane z's closure rather than keeping
             // it live through the chemistry (registers, not ALU, limit it)
 #pragma unroll
-            for (int g = 0; g < G; ++g) m1_pressure(cur[g].n, cur[g].fx, cur[g].fy, cur[g].fz, c, Pc[g]);
+            for (int g = 0; g < G; ++g) m1_pressure(cur[g].n, cur[g].fx, cur[g].fy, cur[g].fz, c, Pc[g], cc);
         }
 
         Vec4<R> us[G];
@@ -540,7 +529,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
                     hv.fz = hd == 2 ? hsgn * hphi[g] : R(0);
                 }
                 R Ph[6];
-                m1_pressure(hv.n, hv.fx, hv.fy, hv.fz, c, Ph);
+                m1_pressure(hv.n, hv.fx, hv.fy, hv.fz, c, Ph, cc);
                 Vec4<R> Ax, Bx, Ay, By;
                 split_xy(hv, Ph, c, Ax, Bx, Ay, By);
                 if (hrole == 0) lAy[buf][0][hlx - 1] = Ay;            // row below the tile
@@ -550,16 +539,16 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
             }
             __syncthreads();
             {
-#pragma clang fp contract(off)
                 const Vec4<R> aL = lAx[buf][ty][tx], bR = lBx[buf][ty][tx + 1];
                 const Vec4<R> aD = lAy[buf][ty][tx], bT = lBy[buf][ty][tx];
-                // sum of the six split vectors (times 2) minus 6 c U, times lam / 2
-                const R s6 = R(6) * c;
+                // U + lam/2 (sum of the six split vectors (times 2) - 6 c U)
+                // = (1 - 3 c lam) U + lam/2 (sum)
                 const R hl = half * a.lam;
-                R n = cur[g].n + hl * ((aL.n + bR.n) + (aD.n + bT.n) + (Az2[g].n + Bz2[g].n) - s6 * cur[g].n);
-                R fx = cur[g].fx + hl * ((aL.fx + bR.fx) + (aD.fx + bT.fx) + (Az2[g].fx + Bz2[g].fx) - s6 * cur[g].fx);
-                R fy = cur[g].fy + hl * ((aL.fy + bR.fy) + (aD.fy + bT.fy) + (Az2[g].fy + Bz2[g].fy) - s6 * cur[g].fy);
-                R fz = cur[g].fz + hl * ((aL.fz + bR.fz) + (aD.fz + bT.fz) + (Az2[g].fz + Bz2[g].fz) - s6 * cur[g].fz);
+                const R k0 = R(1) - R(3) * c * a.lam;
+                R n = k0 * cur[g].n + hl * ((aL.n + bR.n) + (aD.n + bT.n) + (Az2[g].n + Bz2[g].n));
+                R fx = k0 * cur[g].fx + hl * ((aL.fx + bR.fx) + (aD.fx + bT.fx) + (Az2[g].fx + Bz2[g].fx));
+                R fy = k0 * cur[g].fy + hl * ((aL.fy + bR.fy) + (aD.fy + bT.fy) + (Az2[g].fy + Bz2[g].fy));
+                R fz = k0 * cur[g].fz + hl * ((aL.fz + bR.fz) + (aD.fz + bT.fz) + (Az2[g].fz + Bz2[g].fz));
                 if (!a.nolimit) {
                     const int taken = floor_limit_fwd(n, fx, fy, fz, c);
                     if (active) {
@@ -636,7 +625,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (z + 2 == nz && zhi_ghost) nn[g] = ghost4(bd, 5, g, c, nxt[g]);  // nxt = plane nz-1
-            m1_pressure(nn[g].n, nn[g].fx, nn[g].fy, nn[g].fz, c, Pn[g]);
+            m1_pressure(nn[g].n, nn[g].fx, nn[g].fy, nn[g].fz, c, Pn[g], cc);
             Bz2[g] = bz2(nn[g], Pn[g], c);
         }
     };

@@ -56,42 +56,38 @@ template <> struct FastMath<double> {
 
 // Eddington tensor closure (R2-R4 of the readings): P = D N with
 // D = (1 - chi)/2 I + (3 chi - 1)/2 n n^T, f = |F|/(c N) clipped at 1.
-// Written with the reduced flux g = F/(c N) (|g| = f, an O(1) vector), so no
-// square of a tiny |F| appears: for the faint fields ahead of a front, |F|^2
-// underflows to a denormal long before g does.  With q = |g|^2 and
-// s = sqrt(4 - 3q):
-//   a = (1 - chi)/2 N = (1 + s - 2q)/(5 + 2s) N,
-//   (3 chi - 1)/2 n n^T = q h(q) g g^T / q = h(q) g g^T,  h = (6 + 3/(2 + s))/(5 + 2s),
-// free of cancellation at small q; at the clip (q >= 1) chi = 1 and
-// P = N g g^T / q.
+// With s = sqrt(4 - 3 f^2), Levermore's chi = (3 + 4 f^2)/(5 + 2 s) equals
+// (5 - 2 s)/3 exactly (multiply out (5 - 2s)(5 + 2s) = 9 + 12 f^2), so
+//   (1 - chi)/2 = (s - 1)/3 = (1 - f^2)/(1 + s),
+//   (3 chi - 1)/2 = 2 - s = 3 f^2/(2 + s),
+// and with the reduced flux g = F/(c N) (|g| = f, an O(1) vector), q = |g|^2:
+//   P = N [(1 - q)/(1 + s) I + 3/(2 + s) g g^T],
+// both fractions from one reciprocal of (1 + s)(2 + s).  No square of a tiny
+// |F| appears: for the faint fields ahead of a front |F|^2 underflows long
+// before g does.  At the clip (q >= 1) chi = 1 and P = N g g^T / q: with q
+// clamped to 1 inside s and (1 - q), and max(q, 1) folded into the
+// reciprocal, the same expressions give exactly that (s = 1).  N <= 0: g = 0
+// and D = I/3.  P comes out multiplied by `scale` (the transport asks for
+// c^2 P, the flux's form).
 template <typename R>
-__device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6]) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ void m1_pressure(R N, R Fx, R Fy, R Fz, R c, R P[6], R scale = R(1)) {
     using M = FastMath<R>;
-    R a = N * R(1.0 / 3.0), k = R(0);  // chi = 1/3 when N <= 0
-    R gx = R(0), gy = R(0), gz = R(0);
-    if (N > R(0)) {
-        const R icn = M::rcp(c * N);
-        gx = Fx * icn;
-        gy = Fy * icn;
-        gz = Fz * icn;
-        const R q = gx * gx + gy * gy + gz * gz;
-        if (q < R(1)) {
-            const R s = M::sqrt(R(4) - R(3) * q);
-            const R rd = M::rcp(R(5) + R(2) * s);
-            a = (R(1) + s - R(2) * q) * rd * N;
-            k = (R(6) + R(3) * M::rcp(R(2) + s)) * rd * N;
-        } else {  // f clipped at 1: chi = 1, P = N g g^T / q
-            a = R(0);
-            k = N * M::rcp(q);
-        }
-    }
-    P[0] = a + k * gx * gx;
-    P[1] = k * gx * gy;
-    P[2] = k * gx * gz;
-    P[3] = a + k * gy * gy;
-    P[4] = k * gy * gz;
-    P[5] = a + k * gz * gz;
+    const R icn = N > R(0) ? M::rcp(c * N) : R(0);
+    const R gx = Fx * icn, gy = Fy * icn, gz = Fz * icn;
+    const R q = gx * gx + gy * gy + gz * gz;
+    const R qc = q < R(1) ? q : R(1);
+    const R s = M::sqrt(R(4) - R(3) * qc);
+    const R r = M::rcp((R(1) + s) * (R(2) + s) * (q > R(1) ? q : R(1)));
+    const R sN = scale * N;
+    const R a = sN * (R(1) - qc) * (R(2) + s) * r;
+    const R k = R(3) * sN * (R(1) + s) * r;
+    const R kx = k * gx, ky = k * gy, kz = k * gz;
+    P[0] = a + kx * gx;
+    P[1] = kx * gy;
+    P[2] = kx * gz;
+    P[3] = a + ky * gy;
+    P[4] = ky * gz;
+    P[5] = a + kz * gz;
 }
 
 // The floor N* >= 0 and the limiter |F*| <= c N* after the transport update
@@ -110,7 +106,20 @@ __device__ __forceinline__ int floor_limit_fwd(R &n, R &fx, R &fy, R &fz, R c) {
     const R F2 = fx * fx + fy * fy + fz * fz;
     const R cn = c * n;
     if (F2 > cn * cn) {
-        const R sc = cn * FastMath<R>::rcp(FastMath<R>::sqrt(F2));
+        // scale F to |F| = c N.  The hardware single-precision square root
+        // and reciprocal flush operands below the normal range to zero, so a
+        // faint |F|^2 (possible ahead of a front, and with N floored to 0) is
+        // first brought up by 2^100, exactly
+        R sx = fx, sy = fy, sz = fz, sF2 = F2, scn = cn;
+        if (sizeof(R) == 4 && F2 < R(0x1p-100)) {
+            const R up = R(0x1p100);
+            sx *= up;
+            sy *= up;
+            sz *= up;
+            scn *= up;
+            sF2 = sx * sx + sy * sy + sz * sz;
+        }
+        const R sc = scn * FastMath<R>::rcp(FastMath<R>::sqrt(sF2));
         fx *= sc;
         fy *= sc;
         fz *= sc;
