@@ -42,6 +42,8 @@ struct emma_rt_ctx {
     uint32_t *work_count;        // [1]: cells deferred by the first chemistry pass
     uint32_t *work_cells;        // [V]
     int list_blocks;             // grid of the second chemistry pass
+    void *cont;                  // continuation states of the stopped cells (ContBuf)
+    uint32_t cont_cap;
     AdjointScratch adj;
     Bounds<float> bnd_f;   // global boundaries in the storage precision
     Bounds<double> bnd_d;
@@ -182,12 +184,36 @@ static int64_t field_bytes(const emma_rt_config *cfg) {
     return 4 * cfg->n_groups * V * e;  // N and F of all groups
 }
 
+// Slots of the continuation buffer: enough for every stopped cell in the
+// workloads measured (well under 1 % of the cells per step) with a wide
+// margin; cells stopped beyond it are finished by the first pass itself.
+static uint32_t cont_capacity(int64_t V) {
+    int64_t cap = V / 8 > 65536 ? V / 8 : 65536;
+    return (uint32_t)(cap < V ? cap : V);
+}
+
+static int64_t cont_bytes(int G, uint32_t cap) { return (int64_t)cap * ((2 * G + 3) * 8 + 16); }
+
+static ContBuf cont_view(void *base, int G, uint32_t cap) {
+    ContBuf cb;
+    double *d = (double *)base;
+    cb.N = d;
+    cb.Pf = d + (size_t)G * cap;
+    cb.x = d + (size_t)2 * G * cap;
+    cb.e = cb.x + cap;
+    cb.rem = cb.e + cap;
+    cb.st = (int32_t *)(cb.rem + cap);
+    cb.cap = cap;
+    return cb;
+}
+
 extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
     if (config_error(cfg)) return -1;
     const int64_t V = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     int64_t b = field_bytes(cfg);                          // Ns + Fs
     b += 2 * ((V + 31) / 32) * 4;                          // source and refinement masks
     b += V * 4 + 64;                                       // chemistry work list
+    b += cont_bytes(cfg->n_groups, cont_capacity(V));      // continuation states
     b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
     b += kCntSlots * CNT_COUNT * 8;
     b += ((V + 255) / 256) * (cfg->n_groups + 1) * 8 + (cfg->n_groups + 1) * 8;
@@ -209,6 +235,7 @@ static void release(emma_rt_ctx *c) {
     (void)hipFree(c->dsum);
     (void)hipFree(c->work_count);
     (void)hipFree(c->work_cells);
+    (void)hipFree(c->cont);
     adjoint_release(c->adj);
     if (c->ev) {
         for (hipEvent_t e : *c->ev) (void)hipEventDestroy(e);
@@ -239,6 +266,7 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
     const int64_t V = c->grid.V;
     const int G = cfg->n_groups;
     c->mask_words = (V + 31) / 32;
+    c->cont_cap = cont_capacity(V);
     c->diag_blocks = (int)((V + 255) / 256);
     {
         // persistent second chemistry pass: a few waves per SIMD of the device
@@ -261,6 +289,7 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
         {(void **)&c->dsum, (size_t)(G + 1) * 8},
         {(void **)&c->work_count, (size_t)64},
         {(void **)&c->work_cells, (size_t)V * 4},
+        {&c->cont, (size_t)cont_bytes(G, c->cont_cap)},
     };
     for (auto &a : allocs) {
         if (hipMalloc(a.p, a.n) != hipSuccess) {
@@ -335,8 +364,26 @@ static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, dou
     const WorkList wl{c->work_count, c->work_cells};
     const int tb = chem_tb<S>();
     hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST>), dim3((unsigned)((V + tb - 1) / tb)), dim3(tb), 0, c->stream, Ns,
-                       Fs, N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, skip);
+                       Fs, N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, cont_view(c->cont, G, c->cont_cap), skip);
     return check_launch(c, "chemistry");
+}
+
+// Second pass of the split path: the subcycles the first pass stopped,
+// continued from their saved states.
+template <int G, typename S, bool DIAG>
+static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, double *x, double *T, const double *n0,
+                            const SrcTable &src, const GroupConsts &gc, const ChemParams &cp) {
+    const WorkList wl{c->work_count, c->work_cells};
+    const ContBuf cb = cont_view(c->cont, G, c->cont_cap);
+    const unsigned nb = (unsigned)c->list_blocks;
+    Timed t(c, KID_CHEM_LIST);
+    if (cp.otsa && !cp.isothermal)
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, x, T, n0,
+                           c->grid.V, src, gc, cp, c->cnt, wl, cb);
+    else
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, x, T, n0,
+                           c->grid.V, src, gc, cp, c->cnt, wl, cb);
+    return check_launch(c, "k_chem_cont");
 }
 
 static int reset_worklist(emma_rt_ctx *c) {
@@ -414,7 +461,7 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
                               : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, nullptr);
             if (e) return e;
         }
-        if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
+        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, x, T, n0, src, gc, cp)) return e;
     }
     return EMMA_RT_OK;
 }
@@ -578,6 +625,7 @@ static int64_t noalloc_layout(emma_rt_ctx *c, unsigned char *base, int n_src) {
     c->cnt = (unsigned long long *)take((int64_t)kCntSlots * CNT_COUNT * 8);
     c->work_count = (uint32_t *)take(64);
     c->work_cells = (uint32_t *)take(V * 4);
+    c->cont = take(cont_bytes(G, c->cont_cap));
     return off;
 }
 
@@ -595,6 +643,7 @@ extern "C" int emma_rt_step_noalloc(const emma_rt_config *cfg, void *stream, voi
     c.bnd_f = make_bounds<float>(*cfg);
     c.bnd_d = make_bounds<double>(*cfg);
     c.mask_words = (c.grid.V + 31) / 32;
+    c.cont_cap = cont_capacity(c.grid.V);
     int rc = step_args(&c, N, F, x, T, n0, cell, rate, n_src, dt, n_steps);
     if (rc == EMMA_RT_OK) {
         const int64_t need = noalloc_layout(&c, nullptr, n_src);
@@ -676,7 +725,7 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
                                : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, c->refmask);
             if (e) return e;
         }
-        if (int e = launch_chem_list<G, S, DIAG>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp)) return e;
+        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, x, T, n0, src, gc, cp)) return e;
         if (n_ref > 0) {
             Timed t(c, KID_CRTA);
             if (fast)

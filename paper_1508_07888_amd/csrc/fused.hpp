@@ -359,8 +359,11 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
 
 // FULL: every tile is a whole 64 x TY tile (nx % 64 == 0, ny % TY == 0), so
 // every thread owns a cell and no store needs a predicate.
+#ifndef EMMA_FUSED_MIN_BLOCKS
+#define EMMA_FUSED_MIN_BLOCKS 2
+#endif
 template <int G, typename R, bool DIAG, bool FUSE, bool FAST, int TY, int PD, bool FULL>
-__global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? 2 : 1) void k_tiled(TileArgs<R> a) {
+__global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN_BLOCKS : 1) void k_tiled(TileArgs<R> a) {
     // plane z of the current group, double-buffered: only the split vectors a
     // neighbour reads.  Consumer (ty, tx) reads lAx[ty][tx] (left cell's A_x),
     // lBx[ty][tx + 1] (right cell's B_x), lAy[ty][tx] (A_y of the cell below),

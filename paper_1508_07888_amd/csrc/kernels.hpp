@@ -390,27 +390,67 @@ struct WorkList {
 };
 
 // Appends cell i for every lane with defer set: one atomic per wave.
-__device__ inline void defer_push(const WorkList &wl, bool defer, uint32_t i) {
+// Returns the lane's slot in the list (meaningless where defer is not set).
+__device__ inline uint32_t defer_slot(const WorkList &wl, bool defer, uint32_t i) {
     const unsigned long long m = __ballot(defer);
-    if (m == 0) return;
+    if (m == 0) return 0;
     const int lane = threadIdx.x & 63;
     uint32_t base = 0;
     if (lane == __ffsll((long long)m) - 1) base = atomicAdd(wl.count, (uint32_t)__popcll(m));
     base = __shfl(base, __ffsll((long long)m) - 1, 64);
-    if (defer) wl.cells[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    const uint32_t k = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (defer) wl.cells[k] = i;
+    return k;
+}
+
+__device__ inline void defer_push(const WorkList &wl, bool defer, uint32_t i) { (void)defer_slot(wl, defer, i); }
+
+// Subcycle states of the cells the first pass stopped, by work-list slot
+// (structure of arrays, so the second pass reads them coalesced).  Slots at
+// or beyond cap have no state: the first pass finishes those cells itself.
+struct ContBuf {
+    double *N, *Pf;       // [G][cap]
+    double *x, *e, *rem;  // [cap]
+    int32_t *st;          // [4][cap]: substeps, attempts, cap, xclamp
+    uint32_t cap;
+};
+
+template <int G>
+__device__ __forceinline__ void cont_save(const ContBuf &cb, uint32_t k, const SubState<G> &s) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        cb.N[(size_t)g * cb.cap + k] = s.N[g];
+        cb.Pf[(size_t)g * cb.cap + k] = s.Pf[g];
+    }
+    cb.x[k] = s.x;
+    cb.e[k] = s.e;
+    cb.rem[k] = s.rem;
+    cb.st[k] = s.st.substeps;
+    cb.st[(size_t)cb.cap + k] = s.st.attempts;
+    cb.st[2 * (size_t)cb.cap + k] = s.st.cap;
+    cb.st[3 * (size_t)cb.cap + k] = s.st.xclamp;
+}
+
+template <int G>
+__device__ __forceinline__ void cont_load(const ContBuf &cb, uint32_t k, SubState<G> &s) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        s.N[g] = cb.N[(size_t)g * cb.cap + k];
+        s.Pf[g] = cb.Pf[(size_t)g * cb.cap + k];
+    }
+    s.x = cb.x[k];
+    s.e = cb.e[k];
+    s.rem = cb.rem[k];
+    s.st.substeps = cb.st[k];
+    s.st.attempts = cb.st[(size_t)cb.cap + k];
+    s.st.cap = cb.st[2 * (size_t)cb.cap + k];
+    s.st.xclamp = cb.st[3 * (size_t)cb.cap + k];
 }
 
 // The first chemistry pass touches every element exactly once per step: its
-// loads and stores are marked non-temporal (streamed past the caches).
-#ifndef EMMA_CHEM_NT
-#define EMMA_CHEM_NT 1
-#endif
-// F enters the subcycle only through the product of the substeps' factors, so
-// it is read after the subcycle, which keeps it out of the registers the
-// subcycle needs (more waves per SIMD to overlap memory with the FP64 work).
-#ifndef EMMA_CHEM_F_LATE
-#define EMMA_CHEM_F_LATE 1
-#endif
+// loads and stores are non-temporal (streamed past the caches).  F enters the
+// subcycle only through the product of the substeps' factors, so it is read
+// after the subcycle, which keeps it out of the registers the subcycle needs.
 #ifndef EMMA_CHEM_MIN_BLOCKS
 #define EMMA_CHEM_MIN_BLOCKS 1
 #endif
@@ -431,73 +471,121 @@ template <typename S> constexpr int chem_tb() { return sizeof(S) == 4 ? EMMA_CHE
 
 template <typename T>
 __device__ __forceinline__ T stream_ld(const T *p) {
-    if (EMMA_CHEM_NT) return __builtin_nontemporal_load(p);
-    return *p;
+    return __builtin_nontemporal_load(p);
 }
 template <typename T>
 __device__ __forceinline__ void stream_st(T *p, T v) {
-    if (EMMA_CHEM_NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
+    __builtin_nontemporal_store(v, p);
 }
 
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
-// gas state and the cell's source density; writes the end-of-step N, F, x, T,
-// or defers the cell (budget exhausted: nothing written).  F_out = F* Pf with
-// Pf the product of the substeps' factors, as in chem_cell.
+// gas state and the cell's source density; writes the end-of-step N, F, x, T.
+// A cell still short of dt after kChemBudget substeps stops there: its
+// subcycle state goes to the continuation buffer at its work-list slot and
+// k_chem_cont finishes it (nothing written here); without a free slot it
+// finishes here.  F_out = F* Pf with Pf the product of the substeps' factors.
 template <int G, typename S, bool DIAG, bool FAST>
 __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
     const S *__restrict__ Ns, const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
     double *__restrict__ x, double *__restrict__ T, const double *__restrict__ n0, int64_t V, SrcTable src,
-    GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, const uint32_t *__restrict__ skip) {
+    GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, ContBuf cb,
+    const uint32_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    ChemStats st{0, 0, 0, 0};
-    bool deferred = false, done = false;
+    SubState<G> s;
+    s.st = ChemStats{0, 0, 0, 0};
+    bool stopped = false, done = false;
     // skip: one bit per cell, set for the refined cells whose children run
     // the chemistry instead (null: every cell)
-    if (i < V && !(skip && ((skip[i >> 5] >> (i & 31)) & 1u))) {
-        double Nc[G], Sc[G], Pf[G];
+    const bool mine = i < V && !(skip && ((skip[i >> 5] >> (i & 31)) & 1u));
+    double n0c = 0.0, Tc = 0.0, Sc[G];
+    if (mine) {
+        double Nc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) Nc[g] = (double)stream_ld(Ns + (int64_t)g * V + i);
-#if !EMMA_CHEM_F_LATE
-        S Fr[G][3];
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) Fr[g][k] = stream_ld(Fs + ((int64_t)g * 3 + k) * V + i);
-#endif
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
-        double xc = stream_ld(x + i), Tc = stream_ld(T + i);
-        st = chem_cell_nxt<G, FAST>(gc, cp, Nc, Pf, xc, Tc, stream_ld(n0 + i), Sc, kChemBudget, &deferred);
-        if (!deferred) {
+        const double xc = stream_ld(x + i);
+        Tc = stream_ld(T + i);
+        n0c = stream_ld(n0 + i);
+        sub_start<G>(s, cp, Nc, xc, Tc, n0c);
+        stopped = !sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, kChemBudget);
+    }
+    const uint32_t k = defer_slot(wl, stopped, (uint32_t)i);
+    if (stopped) {
+        if (k < cb.cap) cont_save<G>(cb, k, s);
+        else stopped = !sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, 0x7fffffff);  // no slot: finish here
+    }
+    if (mine && !stopped) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                stream_st(N + (int64_t)g * V + i, (S)Nc[g]);
+        for (int g = 0; g < G; ++g) {
+            stream_st(N + (int64_t)g * V + i, (S)s.N[g]);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const int64_t o = ((int64_t)g * 3 + k) * V + i;
-#if EMMA_CHEM_F_LATE
-                    const S f = stream_ld(Fs + o);
-#else
-                    const S f = Fr[g][k];
-#endif
-                    stream_st(F + o, (S)((double)f * Pf[g]));
-                }
+            for (int c = 0; c < 3; ++c) {
+                const int64_t o = ((int64_t)g * 3 + c) * V + i;
+                stream_st(F + o, (S)((double)stream_ld(Fs + o) * s.Pf[g]));
             }
-            stream_st(x + i, xc);
-            stream_st(T + i, Tc);
-            done = true;
-        } else {
-            st = ChemStats{0, 0, 0, 0};
+        }
+        stream_st(x + i, s.x);
+        stream_st(T + i, sub_T<G, FAST>(s, cp, n0c, Tc));
+        done = true;
+    }
+    if (stopped) s.st = ChemStats{0, 0, 0, 0};  // counted by the continuation pass
+    if (DIAG) {
+        wave_count(cnt, CNT_SUB, s.st.substeps);
+        wave_count(cnt, CNT_ATT, s.st.attempts);
+        wave_count(cnt, CNT_CAP, s.st.cap);
+        wave_count(cnt, CNT_XCLAMP, s.st.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, s.st.substeps);
+        wave_hist(cnt, done, s.st.substeps);
+    }
+}
+
+// Second pass of the split path: continues the subcycles the first pass
+// stopped, from their saved states (list slots below the buffer's capacity),
+// grid-stride over the list.  Writes N, F, x, T of those cells.
+template <int G, typename S, bool DIAG, bool FAST>
+__global__ __launch_bounds__(256) void k_chem_cont(const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
+                                                   double *__restrict__ x, double *__restrict__ T,
+                                                   const double *__restrict__ n0, int64_t V, SrcTable src,
+                                                   GroupConsts gc, ChemParams cp, unsigned long long *cnt,
+                                                   WorkList wl, ContBuf cb) {
+    const uint32_t n = min(*wl.count, cb.cap);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    ChemStats tot{0, 0, 0, 0};
+    int maxsub = 0;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const int64_t i = wl.cells[k];
+        SubState<G> s;
+        cont_load<G>(cb, k, s);
+        double Sc[G];
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        const double n0c = n0[i], Tc = T[i];
+        sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, 0x7fffffff);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            N[(int64_t)g * V + i] = (S)s.N[g];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int64_t o = ((int64_t)g * 3 + c) * V + i;
+                F[o] = (S)((double)Fs[o] * s.Pf[g]);
+            }
+        }
+        x[i] = s.x;
+        T[i] = sub_T<G, FAST>(s, cp, n0c, Tc);
+        if (DIAG) {
+            tot.substeps += s.st.substeps;
+            tot.attempts += s.st.attempts;
+            tot.cap += s.st.cap;
+            tot.xclamp += s.st.xclamp;
+            maxsub = max(maxsub, s.st.substeps);
+            atomicAdd(cnt_slot(cnt) + CNT_HIST + substep_bin(s.st.substeps), 1ull);
         }
     }
-    defer_push(wl, deferred, (uint32_t)i);
     if (DIAG) {
-        wave_count(cnt, CNT_SUB, st.substeps);
-        wave_count(cnt, CNT_ATT, st.attempts);
-        wave_count(cnt, CNT_CAP, st.cap);
-        wave_count(cnt, CNT_XCLAMP, st.xclamp);
-        wave_count_max(cnt, CNT_MAXSUB, st.substeps);
-        wave_hist(cnt, done, st.substeps);
+        wave_count(cnt, CNT_SUB, tot.substeps);
+        wave_count(cnt, CNT_ATT, tot.attempts);
+        wave_count(cnt, CNT_CAP, tot.cap);
+        wave_count(cnt, CNT_XCLAMP, tot.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, maxsub);
     }
 }
 

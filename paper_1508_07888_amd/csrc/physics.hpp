@@ -349,6 +349,59 @@ __host__ __device__ __forceinline__ bool substep(const GroupConsts &gc, const Ch
     return true;
 }
 
+// A cell's subcycle between two substeps: everything the remaining substeps
+// need, so that a later pass can continue it exactly where it stopped (the
+// same arithmetic as an uninterrupted subcycle).  F enters only through Pf,
+// the product of the substeps' factors applied to it so far.
+template <int G> struct SubState {
+    double N[G], Pf[G];
+    double x, e, rem;
+    ChemStats st;
+};
+
+// Start of a cell's subcycle over dt (e = 3/2 (1 + x) n0 k_B T).
+template <int G>
+__host__ __device__ __forceinline__ void sub_start(SubState<G> &s, const ChemParams &p, const double (&N)[G],
+                                                   double x, double T, double n0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        s.N[g] = N[g];
+        s.Pf[g] = 1.0;
+    }
+    s.x = x;
+    s.e = 1.5 * n0 * kKB * (1.0 + x) * T;
+    s.rem = p.dt;
+    s.st = ChemStats{0, 0, 0, 0};
+}
+
+// Substeps until dt is covered (true), or until `budget` substeps have been
+// accepted with dt not covered yet (false: s holds the state to continue
+// from).  Tfix: the cell's temperature, used only in isothermal mode.
+template <int G, bool FAST>
+__host__ __device__ __forceinline__ bool sub_run(SubState<G> &s, const GroupConsts &gc, const ChemParams &p,
+                                                 double n0, double Tfix, const double (&S)[G], int budget) {
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    const double eunit = 1.5 * n0 * kKB;
+    while (s.rem > 0.0) {
+        if (s.st.substeps >= budget) return false;
+        const bool last = s.st.substeps >= p.max_substeps;
+        double inv[G];
+        if (!substep<G, FAST>(gc, p, last, n0, eunit, Tfix, S, s.N, s.x, s.e, s.rem, inv, s.st, nullptr)) break;
+#pragma unroll
+        for (int g = 0; g < G; ++g) s.Pf[g] *= inv[g];
+        if (last) { s.st.cap = 1; break; }
+        if (iso) break;
+    }
+    return true;
+}
+
+// End-of-step temperature of a finished subcycle.
+template <int G, bool FAST>
+__host__ __device__ __forceinline__ double sub_T(const SubState<G> &s, const ChemParams &p, double n0, double Tfix) {
+    const bool iso = FAST ? false : (p.isothermal != 0);
+    return iso ? Tfix : s.e / (1.5 * n0 * kKB * (1.0 + s.x));
+}
+
 // The subcycle without F: F only ever gets multiplied by the substeps'
 // factors, so the caller applies their product Pf[g] to F afterwards
 // (F_out = F_in Pf).  Same budget semantics as chem_cell.
