@@ -18,6 +18,7 @@
 #include "../../include/emma_rt.h"
 #include "kernels.hpp"
 #include "fused.hpp"
+#include "step_ws.hpp"
 #include "adjoint.hpp"
 
 using namespace emma;
@@ -418,15 +419,29 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
             S *oN = even ? Ns : N, *oF = even ? Fs : F;
             if (int e = reset_worklist(c)) return e;
             int e;
+            // single precision: the kernel with transport and chemistry waves
+            // (step_ws.hpp); the FP64 state needs twice its LDS, so FP64 keeps
+            // the kernel that runs both on the same waves (fused.hpp)
+            constexpr bool ws = sizeof(S) == 4;
             {
                 Timed t(c, KID_FUSED);
-                e = launch_fused<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
-                                             dt / c->cfg.dx, c->cnt, wl, bounds_of<S>(c));
+                if constexpr (ws)
+                    e = launch_step_ws<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
+                                                   dt / c->cfg.dx, c->cnt, wl, cont_view(c->cont, G, c->cont_cap),
+                                                   bounds_of<S>(c));
+                else
+                    e = launch_fused<G, S, DIAG>(c->stream, iN, iF, oN, oF, x, T, n0, gr, src, gc, cp,
+                                                 dt / c->cfg.dx, c->cnt, wl, bounds_of<S>(c));
             }
             if (e) return fail(c, EMMA_RT_EHIP, "fused kernel launch failed: %s",
                                hipGetErrorString(hipGetLastError()));
-            // deferred cells: N*, F* were written to the output, finish them in place
-            if (int e2 = launch_chem_list<G, S, DIAG>(c, oN, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
+            if constexpr (ws) {
+                // stopped cells: continue from their saved states; their F* is in the output
+                if (int e2 = launch_chem_cont<G, S, DIAG>(c, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
+            } else {
+                // deferred cells: N*, F* were written to the output, finish them in place
+                if (int e2 = launch_chem_list<G, S, DIAG>(c, oN, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
+            }
         }
         if (n_steps & 1) {
             HIP_TRY(c, hipMemcpyAsync(N, Ns, (size_t)G * V * sizeof(S), hipMemcpyDeviceToDevice, c->stream));

@@ -60,6 +60,7 @@ template <typename R> struct TileArgs {
     ChemParams cp;
     unsigned long long *cnt;
     WorkList wl;
+    ContBuf cb;   // continuation states of stopped cells (k_step_ws)
     Bounds<R> bnd;
     int nolimit;  // 1: write the values before the N >= 0 floor and the limiter (split transport)
 };
@@ -75,6 +76,14 @@ __device__ __forceinline__ T ld(const T *base, uint32_t byte_off) {
 template <typename T>
 __device__ __forceinline__ void st(T *base, uint32_t byte_off, T v) {
     *(T *)((char *)base + byte_off) = v;
+}
+// Stores of the split transport's output: read only by the chemistry pass
+// after the whole grid, so they are streamed past the caches (non-temporal;
+// 0.408 against 0.417 ms per step at 256^3).  Loads stay cached: a tile's
+// rows are the halo rows of its neighbours.
+template <typename T>
+__device__ __forceinline__ void st_out(T *base, uint32_t byte_off, T v) {
+    __builtin_nontemporal_store(v, (T *)((char *)base + byte_off));
 }
 
 template <int G, typename R>
@@ -615,10 +624,10 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
         if (active) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                st(a.No + (int64_t)g * V, zc * E, us[g].n);
-                st(a.Fo + (int64_t)(3 * g + 0) * V, zc * E, us[g].fx);
-                st(a.Fo + (int64_t)(3 * g + 1) * V, zc * E, us[g].fy);
-                st(a.Fo + (int64_t)(3 * g + 2) * V, zc * E, us[g].fz);
+                st_out(a.No + (int64_t)g * V, zc * E, us[g].n);
+                st_out(a.Fo + (int64_t)(3 * g + 0) * V, zc * E, us[g].fx);
+                st_out(a.Fo + (int64_t)(3 * g + 1) * V, zc * E, us[g].fy);
+                st_out(a.Fo + (int64_t)(3 * g + 2) * V, zc * E, us[g].fz);
             }
         }
 
@@ -670,6 +679,7 @@ inline TileArgs<S> tile_args(const S *iN, const S *iF, S *oN, S *oF, double *x, 
     a.cp = cp;
     a.cnt = cnt;
     a.wl = wl;
+    a.cb = ContBuf{};
     a.bnd = bnd;
     a.nolimit = 0;
     return a;
