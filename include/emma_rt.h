@@ -133,7 +133,7 @@ typedef struct {
 /* Create a context on the current HIP device.  cfg is copied.  hip_stream is a
  * hipStream_t (NULL = the default stream).  Allocates every piece of scratch
  * the later calls use (transport ping-pong fields, source tables, counters,
- * adjoint tape of adjoint_max_steps steps).  Returns EINVAL for a bad config,
+ * adjoint tape of adjoint_max_steps - 1 steps).  Returns EINVAL for a bad config,
  * ENOMEM when the scratch does not fit; *ctx is NULL on any error. */
 int emma_rt_init(emma_rt_ctx **ctx, const emma_rt_config *cfg, void *hip_stream);
 
@@ -167,7 +167,7 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
  *   N ... n_steps   as emma_rt_step (no diagnostics: src_cell entries outside
  *                   the grid are ignored without a report)
  * Scratch needed, each piece rounded up to 256 bytes: 4 G V e (N and F; e = 4
- * mixed, 8 FP64) + 4 V (work list) + V/8 (source mask) + 12 n_src + 8 G n_src
+ * mixed, 8 FP64) + 4 V (work list) + V/8 (source mask) + 24 n_src + 8 G n_src
  * (source table) + 14336 (counters) + 64 + (16 G + 40) C (continuation states
  * of the chemistry, C = min(V, max(65536, V/8)) slots).  A grid and source list needing more
  * than EMMA_RT_NOALLOC_SCRATCH_BYTES return EINVAL before anything runs (a

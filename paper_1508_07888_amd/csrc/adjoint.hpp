@@ -21,7 +21,8 @@
 namespace emma {
 
 struct AdjointScratch {
-    void *tape;      // [K][state]: N, F (storage type), x, T (double)
+    void *tape;      // [K - 1][state]: N, F (storage type), x, T (double) at steps 1..K-1 of a
+                     // segment (step 0 is the caller's start state)
     double *gU;      // [4 G][V]: dL/d(pre-limiter transport output)
     double *gS;      // [EMMA_RT_MAX_SOURCES][G]: dL/dS per sorted source position
     int64_t tape_bytes_per_step;
@@ -33,10 +34,15 @@ inline int64_t adjoint_state_bytes(const emma_rt_config &cfg) {
     return V * (4 * cfg.n_groups * e + 16);
 }
 
+// Tape slots: the states after steps 1..K-1 of a segment (at least one slot).
+inline int64_t adjoint_tape_slots(const emma_rt_config &cfg) {
+    return cfg.adjoint_max_steps > 1 ? cfg.adjoint_max_steps - 1 : 1;
+}
+
 inline int64_t adjoint_scratch_bytes(const emma_rt_config &cfg) {
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
-    return cfg.adjoint_max_steps * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * 8 +
+    return adjoint_tape_slots(cfg) * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * 8 +
            (int64_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8;
 }
 
@@ -47,7 +53,7 @@ inline int adjoint_alloc(AdjointScratch &a, const emma_rt_config &cfg) {
     a.tape_bytes_per_step = adjoint_state_bytes(cfg);
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
-    if (hipMalloc(&a.tape, (size_t)(cfg.adjoint_max_steps * a.tape_bytes_per_step)) != hipSuccess) return -1;
+    if (hipMalloc(&a.tape, (size_t)(adjoint_tape_slots(cfg) * a.tape_bytes_per_step)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.gU, (size_t)(4 * cfg.n_groups * V * 8)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.gS, (size_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8) != hipSuccess) return -1;
     return 0;
@@ -97,7 +103,10 @@ __host__ __device__ inline void substep_adj(const GroupConsts &gc, const ChemPar
     const bool otsa = FAST ? true : (p.otsa != 0);
     const bool iso = FAST ? false : (p.isothermal != 0);
     const double Tp = info.Tp;
-    const RateSet r = FAST ? rates_at<true>(Tp) : rates_at(Tp, otsa);
+    // the rates at Tp and their temperature derivatives, in one evaluation
+    RateSet r, dr;
+    if (FAST || otsa) rates_and_dT<true>(Tp, r, dr);
+    else rates_and_dT<false>(Tp, r, dr);
     // dtau of the accepted attempt
     double dtau0 = rem;
     if (info.branch) dtau0 = fabs(e * recip_fp64(info.D));
@@ -199,7 +208,6 @@ __host__ __device__ inline void substep_adj(const GroupConsts &gc, const ChemPar
         cooling_adj(r, n0, x, -aD, ar, axs, an0);
     }
     // rates at Tp
-    const RateSet dr = (FAST || otsa) ? rates_dT<true>(Tp, r) : rates_dT<false>(Tp, r);
     const double aTp = ar.alpha * dr.alpha + ar.dalpha * dr.dalpha + ar.beta * dr.beta + ar.crec * dr.crec +
                        ar.cci * dr.cci + ar.cce * dr.cce + ar.cff * dr.cff;
     if (iso) {

@@ -35,6 +35,8 @@ struct emma_rt_ctx {
     int64_t mask_words;
     int64_t *sorted_cell;  // [EMMA_RT_MAX_SOURCES]
     int32_t *sorted_idx;
+    int64_t *tile_key;     // [EMMA_RT_MAX_SOURCES]: sources sorted within tiles
+    int32_t *tile_idx;
     double *S;             // [EMMA_RT_MAX_SOURCES][G]
     unsigned long long *cnt;     // [kCntSlots][CNT_COUNT]
     double *partial;             // [nblk][G+1]
@@ -215,7 +217,7 @@ extern "C" int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg) {
     b += 2 * ((V + 31) / 32) * 4;                          // source and refinement masks
     b += V * 4 + 64;                                       // chemistry work list
     b += cont_bytes(cfg->n_groups, cont_capacity(V));      // continuation states
-    b += (int64_t)EMMA_RT_MAX_SOURCES * (8 + 4 + 8 * cfg->n_groups);
+    b += (int64_t)EMMA_RT_MAX_SOURCES * (2 * (8 + 4) + 8 * cfg->n_groups);
     b += kCntSlots * CNT_COUNT * 8;
     b += ((V + 255) / 256) * (cfg->n_groups + 1) * 8 + (cfg->n_groups + 1) * 8;
     b += adjoint_scratch_bytes(*cfg);
@@ -230,6 +232,8 @@ static void release(emma_rt_ctx *c) {
     (void)hipFree(c->refmask);
     (void)hipFree(c->sorted_cell);
     (void)hipFree(c->sorted_idx);
+    (void)hipFree(c->tile_key);
+    (void)hipFree(c->tile_idx);
     (void)hipFree(c->S);
     (void)hipFree(c->cnt);
     (void)hipFree(c->partial);
@@ -284,6 +288,8 @@ extern "C" int emma_rt_init(emma_rt_ctx **out, const emma_rt_config *cfg, void *
         {(void **)&c->refmask, (size_t)c->mask_words * 4},
         {(void **)&c->sorted_cell, (size_t)EMMA_RT_MAX_SOURCES * 8},
         {(void **)&c->sorted_idx, (size_t)EMMA_RT_MAX_SOURCES * 4},
+        {(void **)&c->tile_key, (size_t)EMMA_RT_MAX_SOURCES * 8},
+        {(void **)&c->tile_idx, (size_t)EMMA_RT_MAX_SOURCES * 4},
         {(void **)&c->S, (size_t)EMMA_RT_MAX_SOURCES * G * 8},
         {(void **)&c->cnt, (size_t)kCntSlots * CNT_COUNT * 8},
         {(void **)&c->partial, (size_t)c->diag_blocks * (G + 1) * 8},
@@ -329,8 +335,10 @@ static int build_sources(emma_rt_ctx *c, const int64_t *cell, const double *rate
     if (int e = check_launch(c, "k_fill_u32")) return e;
     if (n == 0) return EMMA_RT_OK;
     Timed tr(c, KID_SRC);
+    hipLaunchKernelGGL(k_src_tile_sort, dim3((n + kSrcTile - 1) / kSrcTile), dim3(kSrcTile), 0, c->stream, cell, n,
+                       c->grid.V, c->tile_key, c->tile_idx, c->cnt);
     hipLaunchKernelGGL(k_src_rank, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, cell, n, c->grid.V,
-                       c->sorted_cell, c->sorted_idx, c->cnt);
+                       c->tile_key, c->tile_idx, c->sorted_cell, c->sorted_idx);
     if (int e = check_launch(c, "k_src_rank")) return e;
     const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
     hipLaunchKernelGGL(k_src_heads<G>, dim3((n + tb - 1) / tb), dim3(tb), 0, c->stream, c->sorted_cell,
@@ -357,33 +365,41 @@ static int launch_chem_list(emma_rt_ctx *c, const S *inN, const S *inF, S *oN, S
 }
 
 // First chemistry pass over every cell (skip: refined cells, or null).
+// xo, To null: x, T updated in place; else x, T are read only and the
+// results go to xo, To.
 template <int G, typename S, bool DIAG, bool FAST>
-static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, double *x, double *T,
-                       const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp,
+static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, double *x, double *T, double *xo,
+                       double *To, const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp,
                        const uint32_t *skip) {
     const int64_t V = c->grid.V;
     const WorkList wl{c->work_count, c->work_cells};
     const int tb = chem_tb<S>();
-    hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST>), dim3((unsigned)((V + tb - 1) / tb)), dim3(tb), 0, c->stream, Ns,
-                       Fs, N, F, x, T, n0, V, src, gc, cp, c->cnt, wl, cont_view(c->cont, G, c->cont_cap), skip);
+    const ContBuf cb = cont_view(c->cont, G, c->cont_cap);
+    const dim3 nb((unsigned)((V + tb - 1) / tb));
+    if (xo)
+        hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST, true>), nb, dim3(tb), 0, c->stream, Ns, Fs, N, F, x, T, xo, To,
+                           n0, V, src, gc, cp, c->cnt, wl, cb, skip);
+    else
+        hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST, false>), nb, dim3(tb), 0, c->stream, Ns, Fs, N, F, x, T,
+                           nullptr, nullptr, n0, V, src, gc, cp, c->cnt, wl, cb, skip);
     return check_launch(c, "chemistry");
 }
 
 // Second pass of the split path: the subcycles the first pass stopped,
 // continued from their saved states.
 template <int G, typename S, bool DIAG>
-static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, double *x, double *T, const double *n0,
-                            const SrcTable &src, const GroupConsts &gc, const ChemParams &cp) {
+static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
+                            const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp) {
     const WorkList wl{c->work_count, c->work_cells};
     const ContBuf cb = cont_view(c->cont, G, c->cont_cap);
     const unsigned nb = (unsigned)c->list_blocks;
     Timed t(c, KID_CHEM_LIST);
     if (cp.otsa && !cp.isothermal)
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, x, T, n0,
-                           c->grid.V, src, gc, cp, c->cnt, wl, cb);
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, T, xo, To,
+                           n0, c->grid.V, src, gc, cp, c->cnt, wl, cb);
     else
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, x, T, n0,
-                           c->grid.V, src, gc, cp, c->cnt, wl, cb);
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, T, xo,
+                           To, n0, c->grid.V, src, gc, cp, c->cnt, wl, cb);
     return check_launch(c, "k_chem_cont");
 }
 
@@ -437,7 +453,7 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
                                hipGetErrorString(hipGetLastError()));
             if constexpr (ws) {
                 // stopped cells: continue from their saved states; their F* is in the output
-                if (int e2 = launch_chem_cont<G, S, DIAG>(c, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
+                if (int e2 = launch_chem_cont<G, S, DIAG>(c, oF, oN, oF, T, x, T, n0, src, gc, cp)) return e2;
             } else {
                 // deferred cells: N*, F* were written to the output, finish them in place
                 if (int e2 = launch_chem_list<G, S, DIAG>(c, oN, oF, oN, oF, x, T, n0, src, gc, cp)) return e2;
@@ -472,11 +488,12 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
         {
             Timed t(c, KID_CHEM);
             const int e = (cp.otsa && !cp.isothermal)
-                              ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, nullptr)
-                              : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, nullptr);
+                              ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, nullptr, nullptr, n0, src, gc, cp, nullptr)
+                              : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, nullptr, nullptr, n0, src, gc,
+                                                               cp, nullptr);
             if (e) return e;
         }
-        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, x, T, n0, src, gc, cp)) return e;
+        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, T, x, T, n0, src, gc, cp)) return e;
     }
     return EMMA_RT_OK;
 }
@@ -636,6 +653,8 @@ static int64_t noalloc_layout(emma_rt_ctx *c, unsigned char *base, int n_src) {
     c->mask = (uint32_t *)take(c->mask_words * 4);
     c->sorted_cell = (int64_t *)take((int64_t)n_src * 8);
     c->sorted_idx = (int32_t *)take((int64_t)n_src * 4);
+    c->tile_key = (int64_t *)take((int64_t)n_src * 8);
+    c->tile_idx = (int32_t *)take((int64_t)n_src * 4);
     c->S = (double *)take((int64_t)n_src * G * 8);
     c->cnt = (unsigned long long *)take((int64_t)kCntSlots * CNT_COUNT * 8);
     c->work_count = (uint32_t *)take(64);
@@ -736,11 +755,13 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
         if (int e = reset_worklist(c)) return e;
         {
             Timed t(c, KID_CHEM);
-            const int e = fast ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, c->refmask)
-                               : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, n0, src, gc, cp, c->refmask);
+            const int e = fast ? launch_chem<G, S, DIAG, true>(c, Ns, Fs, N, F, x, T, nullptr, nullptr, n0, src, gc, cp,
+                                                               c->refmask)
+                               : launch_chem<G, S, DIAG, false>(c, Ns, Fs, N, F, x, T, nullptr, nullptr, n0, src, gc,
+                                                                cp, c->refmask);
             if (e) return e;
         }
-        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, x, T, n0, src, gc, cp)) return e;
+        if (int e = launch_chem_cont<G, S, DIAG>(c, Fs, N, F, T, x, T, n0, src, gc, cp)) return e;
         if (n_ref > 0) {
             Timed t(c, KID_CRTA);
             if (fast)
@@ -835,6 +856,41 @@ extern "C" int emma_rt_step_crta(emma_rt_ctx *c, void *N, void *F, double *x, do
 }
 
 // ----------------------------------------------------------------- adjoint
+// One step of the split path from the state (iN, iF, ix, iT) into the
+// separate arrays (oN, oF, ox, oT) with the source table already built: the
+// adjoint's forward recompute, tape slot s into slot s + 1 without a copy.
+template <int G, typename S>
+static int split_step_to(emma_rt_ctx *c, const S *iN, const S *iF, const double *ix, const double *iT, S *oN,
+                         S *oF, double *ox, double *oT, const double *n0, int n_src, const ChemParams &cp) {
+    const Grid gr = c->grid;
+    const int tb = 256;
+    const unsigned nblk = (unsigned)((gr.V + tb - 1) / tb);
+    const GroupConsts gc = group_consts(c->cfg);
+    const SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
+    S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
+    const double lam = cp.dt / c->cfg.dx;
+    {
+        Timed t(c, KID_TRANSPORT);
+        if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
+            hipLaunchKernelGGL((k_transport<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, iN, iF, Ns, Fs, gr,
+                               (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+        else
+            launch_transport_tiled<G, S, false>(c->stream, iN, iF, Ns, Fs, gr, cp, lam, c->cnt, bounds_of<S>(c));
+    }
+    if (int e = check_launch(c, "transport (tape)")) return e;
+    if (int e = reset_worklist(c)) return e;
+    {
+        Timed t(c, KID_CHEM);
+        const int e = (cp.otsa && !cp.isothermal)
+                          ? launch_chem<G, S, false, true>(c, Ns, Fs, oN, oF, (double *)ix, (double *)iT, ox, oT,
+                                                           n0, src, gc, cp, nullptr)
+                          : launch_chem<G, S, false, false>(c, Ns, Fs, oN, oF, (double *)ix, (double *)iT, ox, oT,
+                                                            n0, src, gc, cp, nullptr);
+        if (e) return e;
+    }
+    return launch_chem_cont<G, S, false>(c, Fs, oN, oF, iT, ox, oT, n0, src, gc, cp);
+}
+
 template <int G, typename S>
 static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double *x0, const double *T0,
                          const double *n0, const int64_t *cell, const double *rate, int n_src, double dt,
@@ -853,24 +909,21 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     const bool fast = cp.otsa && !cp.isothermal;
     const double lam = dt / c->cfg.dx;
     const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
-    // tape: state at the start of every step of the segment
+    // tape: state at the start of every step of the segment; the first is
+    // the caller's (read only), the others are written by the recompute
     const int64_t step_bytes = c->adj.tape_bytes_per_step;
-    auto tN = [&](int s) { return (S *)((char *)c->adj.tape + s * step_bytes); };
-    auto tF = [&](int s) { return tN(s) + (int64_t)G * V; };
-    auto tx = [&](int s) { return (double *)(tF(s) + (int64_t)3 * G * V); };
-    auto tT = [&](int s) { return tx(s) + V; };
+    auto slot = [&](int s) { return (char *)c->adj.tape + (s - 1) * step_bytes; };
+    auto tN = [&](int s) { return s == 0 ? (S *)N0 : (S *)slot(s); };
+    auto tF = [&](int s) { return s == 0 ? (S *)F0 : (S *)slot(s) + (int64_t)G * V; };
+    auto tx = [&](int s) { return s == 0 ? (double *)x0 : (double *)((S *)slot(s) + (int64_t)4 * G * V); };
+    auto tT = [&](int s) { return s == 0 ? (double *)T0 : tx(s) + V; };
     if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
-    const size_t nb = (size_t)G * V * sizeof(S), fb = 3 * nb, db = (size_t)V * 8;
-    HIP_TRY(c, hipMemcpyAsync(tN(0), N0, nb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(tF(0), F0, fb, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(tx(0), x0, db, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(tT(0), T0, db, hipMemcpyDeviceToDevice, c->stream));
-    for (int s = 0; s + 1 < n_steps; ++s) {
-        HIP_TRY(c, hipMemcpyAsync(tN(s + 1), tN(s), (size_t)step_bytes, hipMemcpyDeviceToDevice, c->stream));
-        // (its kernels are timed under their own kinds: no bracket around a bracket)
-        if (int e = run_steps<G, S, false>(c, tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1), n0, n_src, dt, 1))
+    // the segment forward, step s into tape slot s + 1 (its kernels are timed
+    // under their own kinds)
+    for (int s = 0; s + 1 < n_steps; ++s)
+        if (int e = split_step_to<G, S>(c, tN(s), tF(s), tx(s), tT(s), tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1),
+                                        n0, n_src, cp))
             return e;
-    }
     SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
     if (n_src > 0) {
         hipLaunchKernelGGL(k_fill_f64, dim3((n_src * G + tb - 1) / tb), dim3(tb), 0, c->stream, c->adj.gS,

@@ -125,23 +125,58 @@ __global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v) {
     if (i < n) p[i] = v;
 }
 
-// Rank of each source in the order (cell, list position); cells outside the
-// grid get the key INT64_MAX so they sort last and are ignored.
-__global__ void k_src_rank(const int64_t *cell, int n, int64_t V, int64_t *sorted_cell,
-                           int32_t *sorted_idx, unsigned long long *cnt) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t INV = INT64_MAX;
-    int64_t ks = cell[s];
-    if (ks < 0 || ks >= V) {
-        ks = INV;
-        atomicAdd(cnt_slot(cnt) + CNT_BADSRC, 1ull);
+// Sorting the source list by (cell, list position), cells outside the grid
+// keyed INT64_MAX so that they sort last and are ignored: each block sorts a
+// tile of kSrcTile sources in LDS (rank = number of smaller keys within the
+// tile), then every source's rank in the whole list is the sum over tiles of
+// the number of smaller keys there (a binary search in each sorted tile):
+// O(n (n / kSrcTile) log kSrcTile) work instead of O(n^2).
+constexpr int kSrcTile = 256;
+
+__device__ inline int64_t src_key(const int64_t *cell, int s, int64_t V) {
+    const int64_t k = cell[s];
+    return (k < 0 || k >= V) ? INT64_MAX : k;
+}
+
+__global__ __launch_bounds__(kSrcTile) void k_src_tile_sort(const int64_t *cell, int n, int64_t V,
+                                                            int64_t *tkey, int32_t *tidx,
+                                                            unsigned long long *cnt) {
+    __shared__ int64_t key[kSrcTile];
+    const int t0 = blockIdx.x * kSrcTile, m = min(kSrcTile, n - t0);
+    const int s = t0 + threadIdx.x;
+    int64_t ks = INT64_MAX;
+    if ((int)threadIdx.x < m) {
+        ks = src_key(cell, s, V);
+        if (ks == INT64_MAX) atomicAdd(cnt_slot(cnt) + CNT_BADSRC, 1ull);
     }
+    key[threadIdx.x] = ks;
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+        int rank = 0;
+        for (int t = 0; t < m; ++t) rank += (key[t] < ks) || (key[t] == ks && t < (int)threadIdx.x);
+        tkey[t0 + rank] = ks;
+        tidx[t0 + rank] = s;
+    }
+}
+
+// Rank of source s in the whole list from the sorted tiles; writes the
+// sorted table (cell, list position).
+__global__ void k_src_rank(const int64_t *cell, int n, int64_t V, const int64_t *tkey, const int32_t *tidx,
+                           int64_t *sorted_cell, int32_t *sorted_idx) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t ks = src_key(cell, s, V);
     int rank = 0;
-    for (int t = 0; t < n; ++t) {
-        int64_t kt = cell[t];
-        if (kt < 0 || kt >= V) kt = INV;
-        rank += (kt < ks) || (kt == ks && t < s);
+    for (int t0 = 0; t0 < n; t0 += kSrcTile) {
+        // keys (k, i) of the tile below (ks, s): k < ks, or k == ks and i < s
+        int lo = 0, hi = min(kSrcTile, n - t0);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int64_t k = tkey[t0 + mid];
+            if (k < ks || (k == ks && tidx[t0 + mid] < s)) lo = mid + 1;
+            else hi = mid;
+        }
+        rank += lo;
     }
     sorted_cell[rank] = ks;
     sorted_idx[rank] = s;
@@ -479,17 +514,22 @@ __device__ __forceinline__ void stream_st(T *p, T v) {
 }
 
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
-// gas state and the cell's source density; writes the end-of-step N, F, x, T.
+// gas state (x, T) and the cell's source density; writes the end-of-step N,
+// F, x, T (in place, or into xo, To with OUT).
 // A cell still short of dt after kChemBudget substeps stops there: its
 // subcycle state goes to the continuation buffer at its work-list slot and
 // k_chem_cont finishes it (nothing written here); without a free slot it
 // finishes here.  F_out = F* Pf with Pf the product of the substeps' factors.
-template <int G, typename S, bool DIAG, bool FAST>
+template <int G, typename S, bool DIAG, bool FAST, bool OUT = false>
 __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
     const S *__restrict__ Ns, const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
-    double *__restrict__ x, double *__restrict__ T, const double *__restrict__ n0, int64_t V, SrcTable src,
-    GroupConsts gc, ChemParams cp, unsigned long long *cnt, WorkList wl, ContBuf cb,
-    const uint32_t *__restrict__ skip) {
+    double *__restrict__ x, double *__restrict__ T, double *__restrict__ xo, double *__restrict__ To,
+    const double *__restrict__ n0, int64_t V, SrcTable src, GroupConsts gc, ChemParams cp,
+    unsigned long long *cnt, WorkList wl, ContBuf cb, const uint32_t *__restrict__ skip) {
+    // OUT: x, T are only read and the results go to the distinct arrays xo,
+    // To; otherwise x, T are updated in place (xo, To unused)
+    double *__restrict__ xw = OUT ? xo : x;
+    double *__restrict__ Tw = OUT ? To : T;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     SubState<G> s;
     s.st = ChemStats{0, 0, 0, 0};
@@ -524,8 +564,8 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
                 stream_st(F + o, (S)((double)stream_ld(Fs + o) * s.Pf[g]));
             }
         }
-        stream_st(x + i, s.x);
-        stream_st(T + i, sub_T<G, FAST>(s, cp, n0c, Tc));
+        stream_st(xw + i, s.x);
+        stream_st(Tw + i, sub_T<G, FAST>(s, cp, n0c, Tc));
         done = true;
     }
     if (stopped) s.st = ChemStats{0, 0, 0, 0};  // counted by the continuation pass
@@ -541,10 +581,10 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
 
 // Second pass of the split path: continues the subcycles the first pass
 // stopped, from their saved states (list slots below the buffer's capacity),
-// grid-stride over the list.  Writes N, F, x, T of those cells.
+// grid-stride over the list.  T: the step's input temperature (used in the
+// isothermal mode); writes N, F, xo, To of those cells.
 template <int G, typename S, bool DIAG, bool FAST>
-__global__ __launch_bounds__(256) void k_chem_cont(const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
-                                                   double *__restrict__ x, double *__restrict__ T,
+__global__ __launch_bounds__(256) void k_chem_cont(const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
                                                    const double *__restrict__ n0, int64_t V, SrcTable src,
                                                    GroupConsts gc, ChemParams cp, unsigned long long *cnt,
                                                    WorkList wl, ContBuf cb) {
@@ -569,8 +609,8 @@ __global__ __launch_bounds__(256) void k_chem_cont(const S *__restrict__ Fs, S *
                 F[o] = (S)((double)Fs[o] * s.Pf[g]);
             }
         }
-        x[i] = s.x;
-        T[i] = sub_T<G, FAST>(s, cp, n0c, Tc);
+        xo[i] = s.x;
+        To[i] = sub_T<G, FAST>(s, cp, n0c, Tc);
         if (DIAG) {
             tot.substeps += s.st.substeps;
             tot.attempts += s.st.attempts;

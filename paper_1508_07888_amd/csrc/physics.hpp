@@ -204,38 +204,54 @@ __host__ __device__ __forceinline__ RateSet rates_at(double T, bool otsa) {
     return otsa ? rates_at<true>(T) : rates_at<false>(T);
 }
 
-// d(fit exponent)/dL of hg_fit.
-__host__ __device__ __forceinline__ double hg_slope(double L, double a, double lnb, double c, double d) {
-    const double u = exp_fp64(c * (L - lnb));
-    return a - d * c * u / (1.0 + u);
-}
-
-// Temperature derivatives of every coefficient of rates_at<OTSA>(T), given
-// its values r (dL/dT = -1/T).
+// rates_at together with the temperature derivative of every coefficient
+// (the adjoint needs both at the same temperature; dL/dT = -1/T): ln(lambda)
+// and the inner u = exp(c (L - ln b)) of each fit serve both the value
+// (same operations as rates_at, so the same bits) and the slope of its
+// exponent, d/dL [a L - d ln(1 + u)] = a - d c u / (1 + u).
 template <bool OTSA>
-__host__ __device__ inline RateSet rates_dT(double T, const RateSet &r) {
-    RateSet d;
+__host__ __device__ inline void rates_and_dT(double T, RateSet &r, RateSet &d) {
     const double invT = recip_fp64(T);
     const double lam = 2.0 * kTHI * invT;
     const double L = log_fp64(lam);
+    const double lnT = 12.662275226919286 - L;  // ln(2 T_HI) - L
+    // value exponent a L - d ln(1 + u) and slope a - d c u / (1 + u), u = exp(c (L - ln b))
+    auto fit = [L](double a, double lnb, double c, double dd, double &slope) {
+        const double u = exp_fp64(c * (L - lnb));
+        slope = a - dd * c * u / (1.0 + u);
+        return a * L - dd * log_fp64(1.0 + u);
+    };
+    double sa, sc, sb;
     if (OTSA) {
-        d.alpha = -r.alpha * hg_slope(L, 1.500, 1.007957920399979, 0.407, 2.242) * invT;
+        r.alpha = 2.753e-14 * exp_fp64(fit(1.500, 1.007957920399979, 0.407, 2.242, sa));
+        r.dalpha = 0.0;
+        r.crec = 3.435e-30 * T * exp_fp64(fit(1.970, 0.8109302162163288, 0.376, 3.720, sc));
+        d.alpha = -r.alpha * sa * invT;
         d.dalpha = 0.0;
-        d.crec = r.crec * (1.0 - hg_slope(L, 1.970, 0.8109302162163288, 0.376, 3.720)) * invT;
+        d.crec = r.crec * (1.0 - sc) * invT;
     } else {
-        const double aA = r.alpha, aB = r.alpha - r.dalpha;
-        const double daA = -aA * hg_slope(L, 1.503, -0.6500876910994983, 0.470, 1.923) * invT;
-        const double daB = -aB * hg_slope(L, 1.500, 1.007957920399979, 0.407, 2.242) * invT;
+        double sbB;
+        const double aA = 1.269e-13 * exp_fp64(fit(1.503, -0.6500876910994983, 0.470, 1.923, sa));
+        const double aB = 2.753e-14 * exp_fp64(fit(1.500, 1.007957920399979, 0.407, 2.242, sbB));
+        r.alpha = aA;
+        r.dalpha = aA - aB;
+        r.crec = 1.778e-29 * T * exp_fp64(fit(1.965, -0.6143360001356555, 0.502, 2.697, sc));
+        const double daA = -aA * sa * invT;
+        const double daB = -(r.alpha - r.dalpha) * sbB * invT;
         d.alpha = daA;
         d.dalpha = daA - daB;
-        d.crec = r.crec * (1.0 - hg_slope(L, 1.965, -0.6143360001356555, 0.502, 2.697)) * invT;
+        d.crec = r.crec * (1.0 - sc) * invT;
     }
-    d.beta = r.beta * (-1.5 + 0.5 * lam - hg_slope(L, -1.089, -1.0384583658483626, 0.874, 1.101)) * invT;
+    r.beta = 21.11 * exp_fp64(-1.5 * lnT - 0.5 * lam + fit(-1.089, -1.0384583658483626, 0.874, 1.101, sb));
+    r.cci = kKB * kTHI * r.beta;
+    const double sT = sqrt(T);
+    r.cce = 7.5e-19 * exp_fp64(-118348.0 * invT) * recip_fp64(1.0 + sT * 0.003162277660168379);
+    r.cff = 1.42e-27 * 1.3 * sT;
+    d.beta = r.beta * (-1.5 + 0.5 * lam - sb) * invT;
     d.cci = kKB * kTHI * d.beta;
-    const double sT = sqrt(T), k = 0.003162277660168379;
+    const double k = 0.003162277660168379;
     d.cce = r.cce * (118348.0 * invT * invT - 0.5 * k / sT / (1.0 + k * sT));
     d.cff = 0.5 * r.cff * invT;
-    return d;
 }
 
 // Cooling rate Lambda(n0, x, T) (erg cm^-3 s^-1) with n_e = n_p = x n0 and

@@ -254,3 +254,27 @@ def test_tiny_fields_ahead_of_a_front_stay_finite(precision, scale, check, path)
         e = np.max(np.abs(gpu[0][sl] - ora[0][sl])) / np.max(np.abs(ora[0][sl]))
         print(f"tiny region N: {e:.2e}", flush=True)
         assert e <= (1e-12 if precision == "fp64" else 1e-4)
+
+
+@pytest.mark.parametrize("n_src", [257, 3000])
+def test_long_source_lists(n_src):
+    # many sources (several 256-entry sorting tiles), most cells hosting
+    # several of them, plus entries outside the grid: the sums per cell are in
+    # list order as in the oracle, the outside entries are ignored (and
+    # reported as EINVAL with diagnostics)
+    shape, G = (10, 12, 14), 2
+    k = _random_case(shape, G, 21, n_src=n_src)
+    V = int(np.prod(shape))
+    rng = np.random.default_rng(22)
+    bad = rng.choice(n_src, 7, replace=False)
+    cells = k["cells"].copy()
+    cells[bad[:4]] = V + rng.integers(0, 1000, 4)
+    cells[bad[4:]] = -1 - rng.integers(0, 1000, 3)
+    ok = np.ones(n_src, bool)
+    ok[bad] = False
+    g = groups_for(G)
+    kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=2, groups=g)
+    ora = oracle.run(k["N"], k["F"], k["x"], k["T"], k["n0"], cells[ok], k["rates"][ok], **kw)
+    gpu = run_gpu(k["N"], k["F"], k["x"], k["T"], k["n0"], cells, k["rates"], precision="fp64", **kw)
+    _compare(gpu, ora, "fp64", f"{n_src} sources")
+    assert gpu[4]["status"] == -1  # EINVAL: out-of-grid sources were ignored
