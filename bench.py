@@ -110,6 +110,8 @@ def _kind(name, precision="mixed"):
     product = not (len(targs) > 2 and targs[2] == "true") and len(targs) > 1 and targs[1] == storage
     if "k_tiled" in name:
         return ("fused_step" if targs[3] == "true" else "transport"), product
+    if "k_step_ws<" in name:
+        return "fused_step", product
     if "k_chem<" in name:
         return "chemistry", product
     if "k_transport<" in name:
@@ -678,7 +680,7 @@ def main():
     # the SQ counter summary is of the default command (this workload, split path)
     chem_valu = None
     if args.workload == "throughput256" and args.path == "split":
-        chem_valu = valu_from_profiles("void emma::k_chem<3, float, false, true>")
+        chem_valu = valu_from_profiles("void emma::k_chem<3, float, false, true, false>")
     if chem_valu is not None and "chemistry" in kern:
         n, ms = kern["chemistry"]
         chem_valu.update(valu_issue(chem_valu, mixed["V"] / 64, ms / n * 1e-3))
