@@ -133,7 +133,9 @@ typedef struct {
 /* Create a context on the current HIP device.  cfg is copied.  hip_stream is a
  * hipStream_t (NULL = the default stream).  Allocates every piece of scratch
  * the later calls use (transport ping-pong fields, source tables, counters,
- * adjoint tape of adjoint_max_steps - 1 steps).  Returns EINVAL for a bad config,
+ * adjoint tape of adjoint_max_steps - 1 states; its transport part,
+ * adjoint_max_steps steps of N*, F*, only if the device then still has the
+ * room of four more states free: without it the adjoint recomputes them).  Returns EINVAL for a bad config,
  * ENOMEM when the scratch does not fit; *ctx is NULL on any error. */
 int emma_rt_init(emma_rt_ctx **ctx, const emma_rt_config *cfg, void *hip_stream);
 
@@ -225,7 +227,12 @@ int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double 
  * The floor N >= 0 and the limiter |F| <= c_red N are reversed along the
  * decisions the forward took, with the forward's own arithmetic.
  * The segment is recomputed forward from (N0, F0, x0, T0) into the context's
- * tape.  Every boundary kind is differentiated (an inflow face's beam is a
+ * tape (the states of its steps, the transport output of each step before the
+ * floor and the limiter when that part of the tape was allocated, and which
+ * cells took more than one chemistry substep); then the steps are reversed
+ * from the last.  The call uses a second stream of its own beside the
+ * context's stream and joins it before returning (all its work is ordered
+ * after earlier work on the context's stream).  Every boundary kind is differentiated (an inflow face's beam is a
  * constant); the HLL flux is not (EINVAL).  Returns OK, EINVAL or EHIP. */
 int emma_rt_step_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
                          const double *x0, const double *T0, const double *n_H,
@@ -268,7 +275,8 @@ int emma_rt_profile_enable(emma_rt_ctx *ctx, int32_t enable);
 int emma_rt_profile_read(emma_rt_ctx *ctx, emma_rt_kernel_time *out, int32_t max_out,
                          int32_t *n_out);
 
-/* Size in bytes of the device scratch a context with this config allocates. */
+/* Size in bytes of the device scratch a context with this config allocates
+ * (at most: the adjoint's transport tape is left out when memory is short). */
 int64_t emma_rt_scratch_bytes(const emma_rt_config *cfg);
 
 #ifdef __cplusplus

@@ -23,9 +23,18 @@ namespace emma {
 struct AdjointScratch {
     void *tape;      // [K - 1][state]: N, F (storage type), x, T (double) at steps 1..K-1 of a
                      // segment (step 0 is the caller's start state)
+    void *ustar;     // [K][4 G V] storage type: each step's transport output before the floor
+                     // and the limiter; null when it did not fit (then recomputed)
     double *gU;      // [4 G][V]: dL/d(pre-limiter transport output)
     double *gS;      // [EMMA_RT_MAX_SOURCES][G]: dL/dS per sorted source position
     int64_t tape_bytes_per_step;
+    uint64_t *multi;       // [K][multi_words]: one bit per cell, set where the segment's
+                           // forward subcycle of that step was not a single substep
+    int64_t multi_words;
+    uint32_t *list;        // [V]: the marked cells of one step, compacted
+    uint32_t *list_count;  // [16]
+    hipStream_t side;      // runs the kept-state pass beside the single-substep pass
+    hipEvent_t ev_in, ev_out;
 };
 
 inline int64_t adjoint_state_bytes(const emma_rt_config &cfg) {
@@ -39,33 +48,65 @@ inline int64_t adjoint_tape_slots(const emma_rt_config &cfg) {
     return cfg.adjoint_max_steps > 1 ? cfg.adjoint_max_steps - 1 : 1;
 }
 
+// 64-bit words of one step's bitmask: whole chemistry blocks of up to 256 cells.
+inline int64_t adjoint_multi_words(int64_t V) { return (V + 255) / 256 * 4; }
+
+// Transport tape: K steps of N*, F* in the storage precision.
+inline int64_t adjoint_ustar_bytes(const emma_rt_config &cfg) {
+    const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    return (int64_t)cfg.adjoint_max_steps * 4 * cfg.n_groups * V * (cfg.precision == EMMA_RT_FP64 ? 8 : 4);
+}
+
+// Everything the adjoint allocates, the transport tape included.
 inline int64_t adjoint_scratch_bytes(const emma_rt_config &cfg) {
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
     return adjoint_tape_slots(cfg) * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * 8 +
-           (int64_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8;
+           (int64_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8 +
+           (int64_t)cfg.adjoint_max_steps * adjoint_multi_words(V) * 8 + V * 4 + 64 + adjoint_ustar_bytes(cfg);
 }
 
 inline int adjoint_alloc(AdjointScratch &a, const emma_rt_config &cfg) {
-    a.tape = nullptr;
-    a.gU = nullptr;
-    a.gS = nullptr;
+    a = AdjointScratch{};
     a.tape_bytes_per_step = adjoint_state_bytes(cfg);
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    a.multi_words = adjoint_multi_words(V);
     if (hipMalloc(&a.tape, (size_t)(adjoint_tape_slots(cfg) * a.tape_bytes_per_step)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.gU, (size_t)(4 * cfg.n_groups * V * 8)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.gS, (size_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8) != hipSuccess) return -1;
+    if (hipMalloc((void **)&a.multi, (size_t)(cfg.adjoint_max_steps * a.multi_words * 8)) != hipSuccess) return -1;
+    if (hipMalloc((void **)&a.list, (size_t)V * 4) != hipSuccess) return -1;
+    if (hipMalloc((void **)&a.list_count, 64) != hipSuccess) return -1;
+    if (hipStreamCreateWithFlags(&a.side, hipStreamNonBlocking) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&a.ev_in, hipEventDisableTiming) != hipSuccess) return -1;
+    if (hipEventCreateWithFlags(&a.ev_out, hipEventDisableTiming) != hipSuccess) return -1;
+    // last, and optional: only while the device keeps the room of four more
+    // states free beside it (for the caller's state and gradient arrays);
+    // without it the reverse sweep recomputes each step's transport (same
+    // bits, one more transport per step)
+    size_t free_b = 0, total_b = 0;
+    const int64_t need = adjoint_ustar_bytes(cfg) + 4 * adjoint_state_bytes(cfg);
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (int64_t)free_b >= need &&
+        hipMalloc(&a.ustar, (size_t)adjoint_ustar_bytes(cfg)) != hipSuccess) {
+        a.ustar = nullptr;
+        (void)hipGetLastError();
+    }
     return 0;
 }
 
 inline void adjoint_release(AdjointScratch &a) {
     if (a.tape) (void)hipFree(a.tape);
+    if (a.ustar) (void)hipFree(a.ustar);
     if (a.gU) (void)hipFree(a.gU);
     if (a.gS) (void)hipFree(a.gS);
-    a.tape = nullptr;
-    a.gU = nullptr;
-    a.gS = nullptr;
+    if (a.multi) (void)hipFree(a.multi);
+    if (a.list) (void)hipFree(a.list);
+    if (a.list_count) (void)hipFree(a.list_count);
+    if (a.ev_in) (void)hipEventDestroy(a.ev_in);
+    if (a.ev_out) (void)hipEventDestroy(a.ev_out);
+    if (a.side) (void)hipStreamDestroy(a.side);
+    a = AdjointScratch{};
 }
 
 // ------------------------------------------------------- chemistry adjoint
@@ -513,37 +554,81 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     return true;
 }
 
-// First pass, one thread per cell: single-substep subcycles (95 % of the
-// cell-steps of the 256^3 benchmark); the others are appended to the work
-// list for the kept-state pass.  Handing the first pass subcycles of up to 2
-// or 4 substeps (replayed from the cell's start) measured slower: 3.7 and
-// 4.3 ms per step at 256^3 against 2.4 ms for this split before the
+// First pass, one thread per cell: single-substep subcycles (about 98 % of
+// the cell-steps of the 256^3 benchmark); the others go to the kept-state pass.
+// With `multi` (the segment's forward marked the cells whose subcycle was not
+// a single substep) the marked cells are left to that pass, which runs beside
+// this one; without it, or for a cell the forward did not mark that needs
+// more than one substep all the same, the cell is appended to the work list
+// for a kept-state pass after this one.  Handing the first pass subcycles of
+// up to 2 or 4 substeps (replayed from the cell's start) measured slower: 3.7
+// and 4.3 ms per step at 256^3 against 2.4 ms for this split before the
 // single-substep form.
 // one wave per block, for the reason given at EMMA_CHEM_TB (1.21 ms against
 // 1.29 ms with 256 threads at 256^3)
 #ifndef EMMA_ADJ_TB
 #define EMMA_ADJ_TB 64
 #endif
+// minimum waves per SIMD the register allocation of each adjoint kernel keeps
+#ifndef EMMA_ADJ_CHEM_WAVES
+#define EMMA_ADJ_CHEM_WAVES 1
+#endif
+#ifndef EMMA_ADJ_LIST_WAVES
+#define EMMA_ADJ_LIST_WAVES 1
+#endif
+#ifndef EMMA_ADJ_TRANSPORT_WAVES
+#define EMMA_ADJ_TRANSPORT_WAVES 3
+#endif
 template <int G, typename S, bool FAST>
-__global__ __launch_bounds__(EMMA_ADJ_TB) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
+__global__ __launch_bounds__(EMMA_ADJ_TB, EMMA_ADJ_CHEM_WAVES) void k_chem_adj(const S *__restrict__ Ut, const S *__restrict__ Ft,
                                                   const double *__restrict__ xs, const double *__restrict__ Ts,
                                                   const double *__restrict__ n0, int64_t V, SrcTable src,
                                                   GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
                                                   const S *__restrict__ gF, double *__restrict__ gx,
                                                   double *__restrict__ gT, double *__restrict__ g_n0,
-                                                  double *__restrict__ gS, double *__restrict__ gU, WorkList wl) {
+                                                  double *__restrict__ gS, double *__restrict__ gU, WorkList wl,
+                                                  const uint64_t *__restrict__ multi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool listed = multi && i < V && ((multi[i >> 6] >> (i & 63)) & 1ull);
     bool deferred = false;
-    if (i < V)
+    if (i < V && !listed)
         deferred = !chem_adj_cell<G, S, FAST, -1>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
                                                   gU, 1);
     defer_push(wl, deferred, (uint32_t)i);
 }
 
+// Compaction of one step's bitmask into a cell list: one thread per 64-bit
+// word, one atomic per wave.  The order of the list is not fixed; no result
+// depends on it (every cell's adjoint is computed on its own).
+__global__ __launch_bounds__(256) void k_multi_list(const uint64_t *__restrict__ multi, int64_t words, int64_t V,
+                                                    uint32_t *count, uint32_t *cells) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t w = j < words ? multi[j] : 0ull;
+    if (j == words - 1 && (V & 63)) w &= (1ull << (V & 63)) - 1ull;  // no bits past the grid
+    const uint32_t n = (uint32_t)__popcll(w);
+    uint32_t incl = n;  // inclusive prefix sum over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += t;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (lane == 63 && total) base = atomicAdd(count, total);
+    base = __shfl(base, 63, 64);
+    uint32_t k = base + incl - n;
+    while (w) {
+        const int b = __ffsll((unsigned long long)w) - 1;
+        w &= w - 1ull;
+        cells[k++] = (uint32_t)(j * 64 + b);
+    }
+}
+
 // Second pass over the deferred cells (grid-stride over the list): every
 // substep's start recomputed from the nearest of EMMA_ADJ_KEPT kept states.
 template <int G, typename S, bool FAST>
-__global__ __launch_bounds__(256) void k_chem_adj_list(const S *__restrict__ Ut, const S *__restrict__ Ft,
+__global__ __launch_bounds__(256, EMMA_ADJ_LIST_WAVES) void k_chem_adj_list(const S *__restrict__ Ut, const S *__restrict__ Ft,
                                                        const double *__restrict__ xs, const double *__restrict__ Ts,
                                                        const double *__restrict__ n0, int64_t V, SrcTable src,
                                                        GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
@@ -681,7 +766,7 @@ constexpr int kAdjLZ = 16;
 // from memory: three times the algorithmic bytes); x and y neighbours come
 // through the caches.  Blocks are renumbered per XCD like the forward tiles.
 template <typename S>
-__global__ __launch_bounds__(256) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
+__global__ __launch_bounds__(256, EMMA_ADJ_TRANSPORT_WAVES) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
                                                        const double *__restrict__ gU, S *__restrict__ gN,
                                                        S *__restrict__ gF, Grid gr, double c, double lam,
                                                        Bounds<S> bnd) {

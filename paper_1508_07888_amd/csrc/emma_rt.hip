@@ -365,12 +365,13 @@ static int launch_chem_list(emma_rt_ctx *c, const S *inN, const S *inF, S *oN, S
 }
 
 // First chemistry pass over every cell (skip: refined cells, or null).
-// xo, To null: x, T updated in place; else x, T are read only and the
-// results go to xo, To.
+// xo, To null: x, T updated in place; else the tape form of k_chem: Ns, Fs
+// before the floor and the limiter, x, T read only, the results in xo, To,
+// and with multi the cells whose subcycle was not a single substep.
 template <int G, typename S, bool DIAG, bool FAST>
 static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, double *x, double *T, double *xo,
                        double *To, const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp,
-                       const uint32_t *skip) {
+                       const uint32_t *skip, uint64_t *multi = nullptr) {
     const int64_t V = c->grid.V;
     const WorkList wl{c->work_count, c->work_cells};
     const int tb = chem_tb<S>();
@@ -378,28 +379,41 @@ static int launch_chem(emma_rt_ctx *c, const S *Ns, const S *Fs, S *N, S *F, dou
     const dim3 nb((unsigned)((V + tb - 1) / tb));
     if (xo)
         hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST, true>), nb, dim3(tb), 0, c->stream, Ns, Fs, N, F, x, T, xo, To,
-                           n0, V, src, gc, cp, c->cnt, wl, cb, skip);
+                           n0, V, src, gc, cp, c->cnt, wl, cb, skip, multi);
     else
         hipLaunchKernelGGL((k_chem<G, S, DIAG, FAST, false>), nb, dim3(tb), 0, c->stream, Ns, Fs, N, F, x, T,
-                           nullptr, nullptr, n0, V, src, gc, cp, c->cnt, wl, cb, skip);
+                           nullptr, nullptr, n0, V, src, gc, cp, c->cnt, wl, cb, skip, nullptr);
     return check_launch(c, "chemistry");
 }
 
 // Second pass of the split path: the subcycles the first pass stopped,
-// continued from their saved states.
+// continued from their saved states.  Ns_pre non-null: the tape form (the
+// transport output before the floor and the limiter, see k_chem).
 template <int G, typename S, bool DIAG>
 static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
-                            const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp) {
+                            const double *n0, const SrcTable &src, const GroupConsts &gc, const ChemParams &cp,
+                            const S *Ns_pre = nullptr) {
     const WorkList wl{c->work_count, c->work_cells};
     const ContBuf cb = cont_view(c->cont, G, c->cont_cap);
     const unsigned nb = (unsigned)c->list_blocks;
+    const bool fast = cp.otsa && !cp.isothermal;
     Timed t(c, KID_CHEM_LIST);
-    if (cp.otsa && !cp.isothermal)
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, T, xo, To,
-                           n0, c->grid.V, src, gc, cp, c->cnt, wl, cb);
-    else
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), dim3(nb), dim3(256), 0, c->stream, Fs, N, F, T, xo,
-                           To, n0, c->grid.V, src, gc, cp, c->cnt, wl, cb);
+    const dim3 grid(nb), block(256);
+    const int64_t V = c->grid.V;
+    if (Ns_pre) {
+        if (fast)
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F,
+                               T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb);
+        else
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F,
+                               T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb);
+    } else if (fast) {
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To,
+                           n0, V, src, gc, cp, c->cnt, wl, cb);
+    } else {
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
+                           To, n0, V, src, gc, cp, c->cnt, wl, cb);
+    }
     return check_launch(c, "k_chem_cont");
 }
 
@@ -856,39 +870,44 @@ extern "C" int emma_rt_step_crta(emma_rt_ctx *c, void *N, void *F, double *x, do
 }
 
 // ----------------------------------------------------------------- adjoint
-// One step of the split path from the state (iN, iF, ix, iT) into the
-// separate arrays (oN, oF, ox, oT) with the source table already built: the
-// adjoint's forward recompute, tape slot s into slot s + 1 without a copy.
+// The transport of one step before the floor and the limiter (the forward's
+// own kernel arithmetic), state (iN, iF) into (uN, uF).
 template <int G, typename S>
-static int split_step_to(emma_rt_ctx *c, const S *iN, const S *iF, const double *ix, const double *iT, S *oN,
-                         S *oF, double *ox, double *oT, const double *n0, int n_src, const ChemParams &cp) {
+static int tape_transport(emma_rt_ctx *c, const S *iN, const S *iF, S *uN, S *uF, const ChemParams &cp) {
     const Grid gr = c->grid;
     const int tb = 256;
-    const unsigned nblk = (unsigned)((gr.V + tb - 1) / tb);
+    const double lam = cp.dt / c->cfg.dx;
+    Timed t(c, KID_ADJ_FWD);
+    if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
+        hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3((unsigned)((gr.V + tb - 1) / tb)), dim3(tb), 0,
+                           c->stream, iN, iF, uN, uF, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+    else
+        launch_transport_tiled<G, S, false>(c->stream, iN, iF, uN, uF, gr, cp, lam, c->cnt, bounds_of<S>(c), true);
+    return check_launch(c, "transport (tape)");
+}
+
+// The chemistry of one step from the transport output before the floor and
+// the limiter (uN, uF) and the gas state (ix, iT) into the separate arrays
+// (oN, oF, ox, oT), with the source table already built: the adjoint's
+// forward, tape slot s into slot s + 1 without a copy.  Same bits as the
+// step (the floor and the limiter are the transport's own function, applied
+// at load).  multi: the cells whose subcycle was not a single substep.
+template <int G, typename S>
+static int tape_chem(emma_rt_ctx *c, const S *uN, const S *uF, const double *ix, const double *iT, S *oN, S *oF,
+                     double *ox, double *oT, const double *n0, int n_src, const ChemParams &cp, uint64_t *multi) {
     const GroupConsts gc = group_consts(c->cfg);
     const SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
-    S *Ns = (S *)c->Ns, *Fs = (S *)c->Fs;
-    const double lam = cp.dt / c->cfg.dx;
-    {
-        Timed t(c, KID_TRANSPORT);
-        if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
-            hipLaunchKernelGGL((k_transport<G, S, false>), dim3(nblk), dim3(tb), 0, c->stream, iN, iF, Ns, Fs, gr,
-                               (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
-        else
-            launch_transport_tiled<G, S, false>(c->stream, iN, iF, Ns, Fs, gr, cp, lam, c->cnt, bounds_of<S>(c));
-    }
-    if (int e = check_launch(c, "transport (tape)")) return e;
     if (int e = reset_worklist(c)) return e;
     {
         Timed t(c, KID_CHEM);
         const int e = (cp.otsa && !cp.isothermal)
-                          ? launch_chem<G, S, false, true>(c, Ns, Fs, oN, oF, (double *)ix, (double *)iT, ox, oT,
-                                                           n0, src, gc, cp, nullptr)
-                          : launch_chem<G, S, false, false>(c, Ns, Fs, oN, oF, (double *)ix, (double *)iT, ox, oT,
-                                                            n0, src, gc, cp, nullptr);
+                          ? launch_chem<G, S, false, true>(c, uN, uF, oN, oF, (double *)ix, (double *)iT, ox, oT,
+                                                           n0, src, gc, cp, nullptr, multi)
+                          : launch_chem<G, S, false, false>(c, uN, uF, oN, oF, (double *)ix, (double *)iT, ox, oT,
+                                                            n0, src, gc, cp, nullptr, multi);
         if (e) return e;
     }
-    return launch_chem_cont<G, S, false>(c, Fs, oN, oF, iT, ox, oT, n0, src, gc, cp);
+    return launch_chem_cont<G, S, false>(c, uF, oN, oF, iT, ox, oT, n0, src, gc, cp, uN);
 }
 
 template <int G, typename S>
@@ -898,7 +917,6 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     const Grid gr = c->grid;
     const int64_t V = gr.V;
     const int tb = 256;
-    const unsigned nblk = (unsigned)((V + tb - 1) / tb);
     const GroupConsts gc = group_consts(c->cfg);
     ChemParams cp;
     cp.c = c->cfg.c_red;
@@ -910,54 +928,89 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     const double lam = dt / c->cfg.dx;
     const double vol = c->cfg.dx * c->cfg.dx * c->cfg.dx;
     // tape: state at the start of every step of the segment; the first is
-    // the caller's (read only), the others are written by the recompute
+    // the caller's (read only), the others are written by the segment's
+    // forward.  With the transport tape (ustar), the transport output of
+    // every step before the floor and the limiter is kept too; without it
+    // (it did not fit), the reverse sweep recomputes it into Ns, Fs.
     const int64_t step_bytes = c->adj.tape_bytes_per_step;
     auto slot = [&](int s) { return (char *)c->adj.tape + (s - 1) * step_bytes; };
     auto tN = [&](int s) { return s == 0 ? (S *)N0 : (S *)slot(s); };
     auto tF = [&](int s) { return s == 0 ? (S *)F0 : (S *)slot(s) + (int64_t)G * V; };
     auto tx = [&](int s) { return s == 0 ? (double *)x0 : (double *)((S *)slot(s) + (int64_t)4 * G * V); };
     auto tT = [&](int s) { return s == 0 ? (double *)T0 : tx(s) + V; };
+    const bool keep_u = c->adj.ustar != nullptr;
+    auto uN = [&](int s) { return keep_u ? (S *)c->adj.ustar + (int64_t)s * 4 * G * V : (S *)c->Ns; };
+    auto uF = [&](int s) { return keep_u ? uN(s) + (int64_t)G * V : (S *)c->Fs; };
     if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
-    // the segment forward, step s into tape slot s + 1 (its kernels are timed
-    // under their own kinds)
-    for (int s = 0; s + 1 < n_steps; ++s)
-        if (int e = split_step_to<G, S>(c, tN(s), tF(s), tx(s), tT(s), tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1),
-                                        n0, n_src, cp))
-            return e;
+    // the segment forward, step s into tape slot s + 1, marking the cells whose
+    // subcycle was not a single substep
+    const int64_t mwords = c->adj.multi_words;
+    auto multi = [&](int s) { return c->adj.multi + (int64_t)s * mwords; };
+    for (int s = 0; s < n_steps; ++s) {
+        if (s + 1 < n_steps || keep_u)
+            if (int e = tape_transport<G, S>(c, tN(s), tF(s), uN(s), uF(s), cp)) return e;
+        if (s + 1 < n_steps)
+            if (int e = tape_chem<G, S>(c, uN(s), uF(s), tx(s), tT(s), tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1),
+                                        n0, n_src, cp, multi(s)))
+                return e;
+    }
     SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
     if (n_src > 0) {
         hipLaunchKernelGGL(k_fill_f64, dim3((n_src * G + tb - 1) / tb), dim3(tb), 0, c->stream, c->adj.gS,
                            (int64_t)n_src * G, 0.0);
         if (int e = check_launch(c, "k_fill_f64")) return e;
     }
-    S *Ut = (S *)c->Ns, *Ft = (S *)c->Fs;
     for (int s = n_steps - 1; s >= 0; --s) {
-        {
-            // the transport of step s again, before the floor and the limiter,
-            // with the forward's own kernel arithmetic
-            Timed t(c, KID_ADJ_FWD);
-            if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
-                hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3(nblk), dim3(tb), 0, c->stream, tN(s),
-                                   tF(s), Ut, Ft, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
-            else
-                launch_transport_tiled<G, S, false>(c->stream, tN(s), tF(s), Ut, Ft, gr, cp, lam, c->cnt,
-                                                    bounds_of<S>(c), true);
-        }
-        if (int e = check_launch(c, "k_transport (adjoint recompute)")) return e;
+        if (!keep_u)
+            if (int e = tape_transport<G, S>(c, tN(s), tF(s), uN(s), uF(s), cp)) return e;
+        S *Ut = uN(s), *Ft = uF(s);
         if (int e = reset_worklist(c)) return e;
+        // Cells whose subcycle was more than one substep (marked by the
+        // segment's forward; the last step of the segment has no marks) take
+        // the kept-state pass.  It runs on the side stream beside the
+        // single-substep pass, so its long subcycles overlap the bulk instead
+        // of trailing it (with kernel timing on, both run in turn on the
+        // context's stream).  Cells outside the list that still need more than
+        // one substep go through the work list to a kept-state pass after.
+        const bool marked = s + 1 < n_steps;
+        const bool side = marked && !c->prof;
+        const hipStream_t ls = side ? c->adj.side : c->stream;
+        if (marked) {
+            const int64_t words = (V + 63) / 64;
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->adj.list_count, (int64_t)1, 0u);
+            hipLaunchKernelGGL(k_multi_list, dim3((unsigned)((words + tb - 1) / tb)), dim3(tb), 0, c->stream,
+                               (const uint64_t *)multi(s), words, V, c->adj.list_count, c->adj.list);
+            if (int e = check_launch(c, "k_multi_list")) return e;
+            if (side) {
+                HIP_TRY(c, hipEventRecord(c->adj.ev_in, c->stream));
+                HIP_TRY(c, hipStreamWaitEvent(ls, c->adj.ev_in, 0));
+            }
+            Timed t(c, KID_ADJ_CHEM_LIST);
+            const WorkList ml{c->adj.list_count, c->adj.list};
+            if (fast)
+                hipLaunchKernelGGL((k_chem_adj_list<G, S, true>), dim3(c->list_blocks), dim3(tb), 0, ls, Ut, Ft,
+                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, ml);
+            else
+                hipLaunchKernelGGL((k_chem_adj_list<G, S, false>), dim3(c->list_blocks), dim3(tb), 0, ls, Ut, Ft,
+                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, ml);
+            if (int e = check_launch(c, "k_chem_adj_list (marked cells)")) return e;
+            if (side) HIP_TRY(c, hipEventRecord(c->adj.ev_out, ls));
+        }
         {
             Timed t(c, KID_ADJ_CHEM);
             const WorkList wl{c->work_count, c->work_cells};
+            const uint64_t *ms = marked ? multi(s) : nullptr;
             const int atb = EMMA_ADJ_TB;
             const unsigned ablk = (unsigned)((V + atb - 1) / atb);
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl, ms);
             else
                 hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl, ms);
             if (int e = check_launch(c, "k_chem_adj")) return e;
         }
+        if (side) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->adj.ev_out, 0));
         {
             Timed t(c, KID_ADJ_CHEM_LIST);
             const WorkList wl{c->work_count, c->work_cells};

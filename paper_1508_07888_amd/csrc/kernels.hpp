@@ -515,21 +515,26 @@ __device__ __forceinline__ void stream_st(T *p, T v) {
 
 // One thread per cell: reads the post-transport N*, F* (storage type S), the
 // gas state (x, T) and the cell's source density; writes the end-of-step N,
-// F, x, T (in place, or into xo, To with OUT).
+// F, x, T (in place, or into xo, To with TAPE).
 // A cell still short of dt after kChemBudget substeps stops there: its
 // subcycle state goes to the continuation buffer at its work-list slot and
 // k_chem_cont finishes it (nothing written here); without a free slot it
 // finishes here.  F_out = F* Pf with Pf the product of the substeps' factors.
-template <int G, typename S, bool DIAG, bool FAST, bool OUT = false>
+// TAPE (the adjoint's segment forward): Ns, Fs hold the transport output
+// before the floor and the limiter, which are applied here with the
+// transport's own function (same bits as the step); x, T are only read and
+// the results go to the distinct arrays xo, To; with multi, one bit per cell
+// (one 64-bit word per wave of 64 consecutive cells), set unless the subcycle
+// was a single accepted substep.
+template <int G, typename S, bool DIAG, bool FAST, bool TAPE = false>
 __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
     const S *__restrict__ Ns, const S *__restrict__ Fs, S *__restrict__ N, S *__restrict__ F,
     double *__restrict__ x, double *__restrict__ T, double *__restrict__ xo, double *__restrict__ To,
     const double *__restrict__ n0, int64_t V, SrcTable src, GroupConsts gc, ChemParams cp,
-    unsigned long long *cnt, WorkList wl, ContBuf cb, const uint32_t *__restrict__ skip) {
-    // OUT: x, T are only read and the results go to the distinct arrays xo,
-    // To; otherwise x, T are updated in place (xo, To unused)
-    double *__restrict__ xw = OUT ? xo : x;
-    double *__restrict__ Tw = OUT ? To : T;
+    unsigned long long *cnt, WorkList wl, ContBuf cb, const uint32_t *__restrict__ skip,
+    uint64_t *__restrict__ multi) {
+    double *__restrict__ xw = TAPE ? xo : x;
+    double *__restrict__ Tw = TAPE ? To : T;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     SubState<G> s;
     s.st = ChemStats{0, 0, 0, 0};
@@ -541,7 +546,11 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
     if (mine) {
         double Nc[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) Nc[g] = (double)stream_ld(Ns + (int64_t)g * V + i);
+        for (int g = 0; g < G; ++g) {
+            S n = stream_ld(Ns + (int64_t)g * V + i);
+            if (TAPE && n < S(0)) n = S(0);  // the floor (the limiter leaves N alone)
+            Nc[g] = (double)n;
+        }
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
         const double xc = stream_ld(x + i);
         Tc = stream_ld(T + i);
@@ -558,15 +567,23 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             stream_st(N + (int64_t)g * V + i, (S)s.N[g]);
+            S f[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int64_t o = ((int64_t)g * 3 + c) * V + i;
-                stream_st(F + o, (S)((double)stream_ld(Fs + o) * s.Pf[g]));
+            for (int c = 0; c < 3; ++c) f[c] = stream_ld(Fs + ((int64_t)g * 3 + c) * V + i);
+            if (TAPE) {
+                S n = stream_ld(Ns + (int64_t)g * V + i);
+                floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)cp.c);
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) stream_st(F + ((int64_t)g * 3 + c) * V + i, (S)((double)f[c] * s.Pf[g]));
         }
         stream_st(xw + i, s.x);
         stream_st(Tw + i, sub_T<G, FAST>(s, cp, n0c, Tc));
         done = true;
+    }
+    if (TAPE && multi) {
+        const unsigned long long m = __ballot(mine && !(done && s.st.substeps == 1));
+        if ((threadIdx.x & 63) == 0) multi[i >> 6] = m;
     }
     if (stopped) s.st = ChemStats{0, 0, 0, 0};  // counted by the continuation pass
     if (DIAG) {
@@ -582,9 +599,11 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
 // Second pass of the split path: continues the subcycles the first pass
 // stopped, from their saved states (list slots below the buffer's capacity),
 // grid-stride over the list.  T: the step's input temperature (used in the
-// isothermal mode); writes N, F, xo, To of those cells.
-template <int G, typename S, bool DIAG, bool FAST>
-__global__ __launch_bounds__(256) void k_chem_cont(const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
+// isothermal mode); writes N, F, xo, To of those cells.  TAPE: Ns, Fs are
+// the transport output before the floor and the limiter, as in k_chem (Ns is
+// read only then).
+template <int G, typename S, bool DIAG, bool FAST, bool TAPE = false>
+__global__ __launch_bounds__(256) void k_chem_cont(const S *Ns, const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
                                                    const double *__restrict__ n0, int64_t V, SrcTable src,
                                                    GroupConsts gc, ChemParams cp, unsigned long long *cnt,
                                                    WorkList wl, ContBuf cb) {
@@ -603,11 +622,15 @@ __global__ __launch_bounds__(256) void k_chem_cont(const S *Fs, S *N, S *F, cons
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             N[(int64_t)g * V + i] = (S)s.N[g];
+            S f[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int64_t o = ((int64_t)g * 3 + c) * V + i;
-                F[o] = (S)((double)Fs[o] * s.Pf[g]);
+            for (int c = 0; c < 3; ++c) f[c] = Fs[((int64_t)g * 3 + c) * V + i];
+            if (TAPE) {
+                S n = Ns[(int64_t)g * V + i];
+                floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)cp.c);
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) F[((int64_t)g * 3 + c) * V + i] = (S)((double)f[c] * s.Pf[g]);
         }
         xo[i] = s.x;
         To[i] = sub_T<G, FAST>(s, cp, n0c, Tc);

@@ -274,7 +274,10 @@ def test_adjoint_argument_errors():
 def test_kernel_timing_through_an_adjoint_call():
     # regression: the tape's forward steps were bracketed twice (an outer
     # bracket around the step's own per-kernel brackets), which left events
-    # unrecorded and made the profile read fail
+    # unrecorded and made the profile read fail.  Also: with timing off the
+    # kept-state pass over the cells the segment's forward marked runs on a
+    # second stream beside the single-substep pass; with timing on, on the
+    # context's stream after it.  Both orders give the same bits.
     w = E.make_workload("adjoint64", n=16)
     G, shape = w["G"], w["shape"]
     K = 4
@@ -282,16 +285,34 @@ def test_kernel_timing_through_an_adjoint_call():
     N0, F0, x0, T0 = to_dev(w["N"]), to_dev(w["F"]), to_dev(w["x"]), to_dev(w["T"])
     n0 = to_dev(w["n0"])
     cells, rates = to_dev(w["src_cell"], torch.int64), to_dev(w["src_rate"])
-    gN, gF, gT = torch.zeros_like(N0), torch.zeros_like(F0), torch.zeros_like(T0)
-    gx = torch.ones_like(x0)
-    g_n0, g_rate = torch.zeros_like(n0), torch.zeros_like(rates)
+
+    def adjoint():
+        gN, gF, gT = torch.zeros_like(N0), torch.zeros_like(F0), torch.zeros_like(T0)
+        gx = torch.ones_like(x0)
+        g_n0, g_rate = torch.zeros_like(n0), torch.zeros_like(rates)
+        rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in (gN, gF, gx, gT, g_n0, g_rate)]
+
+    # more than one substep somewhere, so the marked-cell pass has work
+    N, F, x, T = N0.clone(), F0.clone(), x0.clone(), T0.clone()
+    d = rt.step(N, F, x, T, n0, cells, rates, w["dt"], n_steps=K - 1, diag=True, raise_on_status=False)
+    assert d["max_sub"] > 1
+    side = adjoint()
     rt.profile(True)
     rt.profile_read()
-    rt.step_adjoint(N0, F0, x0, T0, n0, cells, rates, w["dt"], K, gN, gF, gx, gT, g_n0, g_rate)
+    serial = adjoint()
     kern = rt.profile_read()
     rt.profile(False)
     rt.close()
-    for kind, launches in (("transport", K - 1), ("chemistry", K - 1), ("adj_forward", K), ("adj_chemistry", K),
-                           ("adj_chemistry_deferred", K), ("adj_transport", K), ("adj_sources", 1)):
+    for a, b in zip(side, serial):
+        assert np.array_equal(a, b)
+    assert np.all(np.isfinite(side[4])) and np.any(side[4] != 0)
+    # the segment's transport (every step, kept on the tape) is timed as the
+    # adjoint's forward; the marked-cell pass (steps 0..K-2) and the work-list
+    # pass (every step) are both timed as the deferred chemistry adjoint
+    assert "transport" not in kern
+    for kind, launches in (("chemistry", K - 1), ("adj_forward", K), ("adj_chemistry", K),
+                           ("adj_chemistry_deferred", 2 * K - 1), ("adj_transport", K), ("adj_sources", 1)):
         assert kern[kind][0] == launches, (kind, kern[kind])
         assert kern[kind][1] > 0.0
