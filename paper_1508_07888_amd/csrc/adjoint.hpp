@@ -25,7 +25,7 @@ struct AdjointScratch {
                      // segment (step 0 is the caller's start state)
     void *ustar;     // [K][4 G V] storage type: each step's transport output before the floor
                      // and the limiter; null when it did not fit (then recomputed)
-    double *gU;      // [4 G][V]: dL/d(pre-limiter transport output)
+    void *gU;        // [4 G][V] storage type: dL/d(pre-limiter transport output)
     double *gS;      // [EMMA_RT_MAX_SOURCES][G]: dL/dS per sorted source position
     int64_t tape_bytes_per_step;
     uint64_t *multi;       // [K][multi_words]: one bit per cell, set where the segment's
@@ -61,7 +61,8 @@ inline int64_t adjoint_ustar_bytes(const emma_rt_config &cfg) {
 inline int64_t adjoint_scratch_bytes(const emma_rt_config &cfg) {
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
-    return adjoint_tape_slots(cfg) * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * 8 +
+    const int64_t elem = cfg.precision == EMMA_RT_FP64 ? 8 : 4;
+    return adjoint_tape_slots(cfg) * adjoint_state_bytes(cfg) + 4 * cfg.n_groups * V * elem +
            (int64_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8 +
            (int64_t)cfg.adjoint_max_steps * adjoint_multi_words(V) * 8 + V * 4 + 64 + adjoint_ustar_bytes(cfg);
 }
@@ -71,9 +72,10 @@ inline int adjoint_alloc(AdjointScratch &a, const emma_rt_config &cfg) {
     a.tape_bytes_per_step = adjoint_state_bytes(cfg);
     if (cfg.adjoint_max_steps < 1) return 0;
     const int64_t V = (int64_t)cfg.nx * cfg.ny * cfg.nz;
+    const int64_t elem = cfg.precision == EMMA_RT_FP64 ? 8 : 4;
     a.multi_words = adjoint_multi_words(V);
     if (hipMalloc(&a.tape, (size_t)(adjoint_tape_slots(cfg) * a.tape_bytes_per_step)) != hipSuccess) return -1;
-    if (hipMalloc((void **)&a.gU, (size_t)(4 * cfg.n_groups * V * 8)) != hipSuccess) return -1;
+    if (hipMalloc(&a.gU, (size_t)(4 * cfg.n_groups * V * elem)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.gS, (size_t)EMMA_RT_MAX_SOURCES * cfg.n_groups * 8) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.multi, (size_t)(cfg.adjoint_max_steps * a.multi_words * 8)) != hipSuccess) return -1;
     if (hipMalloc((void **)&a.list, (size_t)V * 4) != hipSuccess) return -1;
@@ -501,7 +503,7 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
                                      const double *__restrict__ n0, int64_t V, const SrcTable &src,
                                      const GroupConsts &gc, const ChemParams &cp, const S *__restrict__ gN,
                                      const S *__restrict__ gF, double *__restrict__ gx, double *__restrict__ gT,
-                                     double *__restrict__ g_n0, double *__restrict__ gS, double *__restrict__ gU,
+                                     double *__restrict__ g_n0, double *__restrict__ gS, S *__restrict__ gU,
                                      int budget) {
     const double c = cp.c;
     double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], aNo[G], aFo[G][3], Sc[G];
@@ -538,10 +540,10 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     for (int g = 0; g < G; ++g) {
         floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, taken[g], aN[g], aF[g][0], aF[g][1],
                         aF[g][2]);
-        gU[(int64_t)(4 * g) * V + i] = aN[g];
-        gU[(int64_t)(4 * g + 1) * V + i] = aF[g][0];
-        gU[(int64_t)(4 * g + 2) * V + i] = aF[g][1];
-        gU[(int64_t)(4 * g + 3) * V + i] = aF[g][2];
+        gU[(int64_t)(4 * g) * V + i] = (S)aN[g];
+        gU[(int64_t)(4 * g + 1) * V + i] = (S)aF[g][0];
+        gU[(int64_t)(4 * g + 2) * V + i] = (S)aF[g][1];
+        gU[(int64_t)(4 * g + 3) * V + i] = (S)aF[g][2];
     }
     gx[i] = ax;
     gT[i] = aT;
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(EMMA_ADJ_TB, EMMA_ADJ_CHEM_WAVES) void k_chem_adj(c
                                                   GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
                                                   const S *__restrict__ gF, double *__restrict__ gx,
                                                   double *__restrict__ gT, double *__restrict__ g_n0,
-                                                  double *__restrict__ gS, double *__restrict__ gU, WorkList wl,
+                                                  double *__restrict__ gS, S *__restrict__ gU, WorkList wl,
                                                   const uint64_t *__restrict__ multi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool listed = multi && i < V && ((multi[i >> 6] >> (i & 63)) & 1ull);
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(256, EMMA_ADJ_LIST_WAVES) void k_chem_adj_list(cons
                                                        GroupConsts gc, ChemParams cp, const S *__restrict__ gN,
                                                        const S *__restrict__ gF, double *__restrict__ gx,
                                                        double *__restrict__ gT, double *__restrict__ g_n0,
-                                                       double *__restrict__ gS, double *__restrict__ gU,
+                                                       double *__restrict__ gS, S *__restrict__ gU,
                                                        WorkList wl) {
     const uint32_t n = *wl.count;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -719,7 +721,7 @@ __host__ __device__ __forceinline__ void flux_jac_t(const ClosureJac &J, int d, 
 // non-periodic face).
 template <typename S>
 __device__ __forceinline__ void transport_adj_cell(double n, const double (&Fv)[3], const double (&gi)[4],
-                                                   const double (&vnb)[3][2][4], const Nbrs &nb, double c,
+                                                   const S (&vnb)[3][2][4], const Nbrs &nb, double c,
                                                    double lam, const Bounds<S> &bnd, double (&out)[4]) {
     const double hl = 0.5 * lam;
     const ClosureJac J = closure_jac(n, Fv[0], Fv[1], Fv[2], c);
@@ -730,10 +732,10 @@ __device__ __forceinline__ void transport_adj_cell(double n, const double (&Fv)[
         // ordinary neighbours: (lam/2) [c (v+ + v-) + M_d(U)^T (v+ - v-)]
         double dv[4], m[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dv[q] = vnb[d][1][q] - vnb[d][0][q];
+        for (int q = 0; q < 4; ++q) dv[q] = (double)vnb[d][1][q] - (double)vnb[d][0][q];
         flux_jac_t(J, d, c, dv, m);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] += hl * (c * (vnb[d][1][q] + vnb[d][0][q]) + m[q]);
+        for (int q = 0; q < 4; ++q) out[q] += hl * (c * ((double)vnb[d][1][q] + (double)vnb[d][0][q]) + m[q]);
         // ghosts of this cell across its own non-periodic faces
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -767,7 +769,7 @@ constexpr int kAdjLZ = 16;
 // through the caches.  Blocks are renumbered per XCD like the forward tiles.
 template <typename S>
 __global__ __launch_bounds__(256, EMMA_ADJ_TRANSPORT_WAVES) void k_transport_adj(const S *__restrict__ N, const S *__restrict__ F,
-                                                       const double *__restrict__ gU, S *__restrict__ gN,
+                                                       const S *__restrict__ gU, S *__restrict__ gN,
                                                        S *__restrict__ gF, Grid gr, double c, double lam,
                                                        Bounds<S> bnd) {
     const int g = blockIdx.y;
@@ -780,39 +782,50 @@ __global__ __launch_bounds__(256, EMMA_ADJ_TRANSPORT_WAVES) void k_transport_adj
     if (x >= gr.nx || y >= gr.ny || z0 >= gr.nz) return;  // no barriers below
     const int z1 = min(z0 + kAdjLZ, gr.nz);
     const int64_t plane = (int64_t)gr.nx * gr.ny;
-    const double *gUg = gU + (int64_t)(4 * g) * V;
-    const S *Ng = N + (int64_t)g * V;
-    const S *Fg = F + (int64_t)(3 * g) * V;
-    S *gNg = gN + (int64_t)g * V;
-    S *gFg = gF + (int64_t)(3 * g) * V;
+    // restrict on the group's views too: the stores of one plane must not
+    // hold back the loads of the next
+    const S *__restrict__ gUg = gU + (int64_t)(4 * g) * V;
+    const S *__restrict__ Ng = N + (int64_t)g * V;
+    const S *__restrict__ Fg = F + (int64_t)(3 * g) * V;
+    S *__restrict__ gNg = gN + (int64_t)g * V;
+    S *__restrict__ gFg = gF + (int64_t)(3 * g) * V;
     int64_t i = (int64_t)z0 * plane + (int64_t)y * gr.nx + x;
-    double below[4], here[4], above[4];
+    // dL/dU* values stay in the storage type until used.  Every neighbour
+    // index is inside the grid (a cell's own index across a non-periodic
+    // face), so the loads are unconditional and a ghost's value is selected
+    // away afterwards: conditional loads each waited for their own data.
+    S below[4], here[4], above[4];
     {
         const Nbrs nb = neighbours(gr, bnd, i, x, y, z0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            below[q] = nb.face[2][0] < 0 ? gUg[(int64_t)q * V + nb.idx[2][0]] : 0.0;
+            const S v = gUg[(int64_t)q * V + nb.idx[2][0]];
+            below[q] = nb.face[2][0] < 0 ? v : S(0);
             here[q] = gUg[(int64_t)q * V + i];
         }
     }
     for (int z = z0; z < z1; ++z, i += plane) {
         const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
-        double vnb[3][2][4];
+        S vnb[3][2][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            above[q] = nb.face[2][1] < 0 ? gUg[(int64_t)q * V + nb.idx[2][1]] : 0.0;
+            const S va = gUg[(int64_t)q * V + nb.idx[2][1]];
+            above[q] = nb.face[2][1] < 0 ? va : S(0);
 #pragma unroll
             for (int d = 0; d < 2; ++d)
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    vnb[d][s][q] = nb.face[d][s] < 0 ? gUg[(int64_t)q * V + nb.idx[d][s]] : 0.0;
+                for (int s = 0; s < 2; ++s) {
+                    const S v = gUg[(int64_t)q * V + nb.idx[d][s]];
+                    vnb[d][s][q] = nb.face[d][s] < 0 ? v : S(0);
+                }
             vnb[2][0][q] = below[q];
             vnb[2][1][q] = above[q];
         }
         const double n = (double)Ng[i];
         const double Fv[3] = {(double)Fg[i], (double)Fg[V + i], (double)Fg[2 * V + i]};
+        const double hd[4] = {(double)here[0], (double)here[1], (double)here[2], (double)here[3]};
         double out[4];
-        transport_adj_cell<S>(n, Fv, here, vnb, nb, c, lam, bnd, out);
+        transport_adj_cell<S>(n, Fv, hd, vnb, nb, c, lam, bnd, out);
         gNg[i] = (S)out[0];
 #pragma unroll
         for (int k = 0; k < 3; ++k) gFg[(int64_t)k * V + i] = (S)out[1 + k];

@@ -989,10 +989,10 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
             const WorkList ml{c->adj.list_count, c->adj.list};
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj_list<G, S, true>), dim3(c->list_blocks), dim3(tb), 0, ls, Ut, Ft,
-                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, ml);
+                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, ml);
             else
                 hipLaunchKernelGGL((k_chem_adj_list<G, S, false>), dim3(c->list_blocks), dim3(tb), 0, ls, Ut, Ft,
-                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, ml);
+                                   tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, ml);
             if (int e = check_launch(c, "k_chem_adj_list (marked cells)")) return e;
             if (side) HIP_TRY(c, hipEventRecord(c->adj.ev_out, ls));
         }
@@ -1004,10 +1004,10 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
             const unsigned ablk = (unsigned)((V + atb - 1) / atb);
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl, ms);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms);
             else
                 hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, c->adj.gU, wl, ms);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms);
             if (int e = check_launch(c, "k_chem_adj")) return e;
         }
         if (side) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->adj.ev_out, 0));
@@ -1017,11 +1017,11 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj_list<G, S, true>), dim3(c->list_blocks), dim3(tb), 0, c->stream, Ut,
                                    Ft, tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS,
-                                   c->adj.gU, wl);
+                                   (S *)c->adj.gU, wl);
             else
                 hipLaunchKernelGGL((k_chem_adj_list<G, S, false>), dim3(c->list_blocks), dim3(tb), 0, c->stream, Ut,
                                    Ft, tx(s), tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS,
-                                   c->adj.gU, wl);
+                                   (S *)c->adj.gU, wl);
         }
         if (int e = check_launch(c, "k_chem_adj_list")) return e;
         {
@@ -1029,7 +1029,7 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
             const unsigned tiles = (unsigned)(((gr.nx + 63) / 64) * ((gr.ny + 3) / 4) *
                                               ((gr.nz + kAdjLZ - 1) / kAdjLZ));
             hipLaunchKernelGGL((k_transport_adj<S>), dim3(tiles, G), dim3(tb), 0, c->stream, tN(s), tF(s),
-                               c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+                               (S *)c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
         }
         if (int e = check_launch(c, "k_transport_adj")) return e;
     }
