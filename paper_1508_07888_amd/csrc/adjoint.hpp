@@ -504,17 +504,28 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
                                      const GroupConsts &gc, const ChemParams &cp, const S *__restrict__ gN,
                                      const S *__restrict__ gF, double *__restrict__ gx, double *__restrict__ gT,
                                      double *__restrict__ g_n0, double *__restrict__ gS, S *__restrict__ gU,
-                                     int budget) {
+                                     int budget, bool skip = false) {
     const double c = cp.c;
     double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], aNo[G], aFo[G][3], Sc[G];
     int taken[G];
+    // every group's values are loaded before any is used: the floor and the
+    // limiter branch, and loads behind a branch would wait group by group
+    S un[G], uf[G][3], gn[G], gf[G][3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        un[g] = Ut[(int64_t)g * V + i];
+        gn[g] = gN[(int64_t)g * V + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uf[g][k] = Ft[((int64_t)g * 3 + k) * V + i];
+            gf[g][k] = gF[((int64_t)g * 3 + k) * V + i];
+        }
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         // the forward's floor and limiter, in its own precision and arithmetic
-        S n = Ut[(int64_t)g * V + i];
-        S f[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) f[k] = Ft[((int64_t)g * 3 + k) * V + i];
+        S n = un[g];
+        S f[3] = {uf[g][0], uf[g][1], uf[g][2]};
         Npre[g] = (double)n;
 #pragma unroll
         for (int k = 0; k < 3; ++k) Fpre[g][k] = (double)f[k];
@@ -522,9 +533,9 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
         Nst[g] = (double)n;
 #pragma unroll
         for (int k = 0; k < 3; ++k) Fst[g][k] = (double)f[k];
-        aNo[g] = (double)gN[(int64_t)g * V + i];
+        aNo[g] = (double)gn[g];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) aFo[g][k] = (double)gF[((int64_t)g * 3 + k) * V + i];
+        for (int k = 0; k < 3; ++k) aFo[g][k] = (double)gf[g][k];
     }
     source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
     double aN[G], aF[G][3], aS[G], ax, aT, an0;
@@ -535,6 +546,10 @@ __device__ inline bool chem_adj_cell(int64_t i, const S *__restrict__ Ut, const 
     else
         chem_cell_adj<G, FAST, (M < 0 ? 0 : M)>(gc, cp, Nst, Fst, xs[i], Ts[i], n0[i], Sc, aNo, aFo, gx[i], gT[i],
                                                 aN, aF, ax, aT, an0, aS, budget, &deferred);
+    // skip (the cell belongs to another pass) is tested only here, so that
+    // its own load does not hold back the cell's loads: the lane computes
+    // with its wave and writes nothing
+    if (skip) return true;
     if (deferred) return false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -591,11 +606,13 @@ __global__ __launch_bounds__(EMMA_ADJ_TB, EMMA_ADJ_CHEM_WAVES) void k_chem_adj(c
                                                   double *__restrict__ gS, S *__restrict__ gU, WorkList wl,
                                                   const uint64_t *__restrict__ multi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool listed = multi && i < V && ((multi[i >> 6] >> (i & 63)) & 1ull);
+    uint64_t mw = 0;
+    if (multi) mw = multi[min(i, V - 1) >> 6];  // same branch for every lane
+    const bool listed = (mw >> (i & 63)) & 1ull;
     bool deferred = false;
-    if (i < V && !listed)
+    if (i < V)
         deferred = !chem_adj_cell<G, S, FAST, -1>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
-                                                  gU, 1);
+                                                  gU, 1, listed);
     defer_push(wl, deferred, (uint32_t)i);
 }
 

@@ -551,10 +551,12 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
             if (TAPE && n < S(0)) n = S(0);  // the floor (the limiter leaves N alone)
             Nc[g] = (double)n;
         }
-        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        // the gas state is loaded before the source lookup branches, so that
+        // all of the cell's loads are in flight together
         const double xc = stream_ld(x + i);
         Tc = stream_ld(T + i);
         n0c = stream_ld(n0 + i);
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
         sub_start<G>(s, cp, Nc, xc, Tc, n0c);
         stopped = !sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, kChemBudget);
     }
