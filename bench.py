@@ -37,6 +37,14 @@ def algorithmic_bytes(kernel, G, elem):
         return 2 * nf
     if kernel in ("chemistry", "fused_step", "step"):
         return 2 * nf + 3 * 8 + 2 * 8
+    # adjoint, per cell-step: the chemistry adjoint reads U* (before the floor
+    # and limiter), x, T, n0, dL/dN, dL/dF, dL/dx, dL/dT and dL/dn0 and writes
+    # dL/dU* (storage type), dL/dx, dL/dT and dL/dn0; the transport adjoint
+    # reads N, F and dL/dU* and writes dL/dN, dL/dF
+    if kernel == "adj_chemistry":
+        return 3 * nf + 3 * 8 + 2 * 8 + 2 * 8 + 2 * 8
+    if kernel == "adj_transport":
+        return 3 * nf
     return None
 
 
@@ -108,6 +116,12 @@ def _kind(name, precision="mixed"):
     targs = [t.strip() for t in name[name.index("<") + 1:name.index(">")].split(",")]
     storage = "float" if precision == "mixed" else "double"
     product = not (len(targs) > 2 and targs[2] == "true") and len(targs) > 1 and targs[1] == storage
+    if "k_chem_adj_list<" in name:
+        return "adj_chemistry_deferred", targs[1] == storage
+    if "k_chem_adj<" in name:
+        return "adj_chemistry", targs[1] == storage
+    if "k_transport_adj<" in name:
+        return "adj_transport", targs[0] == storage
     if "k_tiled" in name:
         return ("fused_step" if targs[3] == "true" else "transport"), product
     if "k_step_ws<" in name:
@@ -462,9 +476,16 @@ def run_adjoint(w, precision, K=10, reps=3):
     finite = bool(torch.isfinite(g_n0).all().item() and torch.isfinite(g_rate).all().item())
     rt.close()
     med = statistics.median(ms)
-    return {"ms_per_step": med, "cell_steps_per_s": w["n0"].size / (med * 1e-3), "K": K,
+    V = w["n0"].size
+    elem = 4 if precision == "mixed" else 8
+    fracs = {}
+    for k, (n, kms) in kern.items():
+        b = algorithmic_bytes(k, G, elem) if k.startswith("adj_") else None
+        if b is not None and kms > 0:
+            fracs[k] = b * V * K / (kms * 1e-3) / HBM_PEAK
+    return {"ms_per_step": med, "cell_steps_per_s": V / (med * 1e-3), "K": K,
             "scratch_GB": rt_scratch_gb(w, precision, K), "gradients_finite": finite,
-            "kernels_ms_per_step": {k: v[1] / K for k, v in kern.items()}}
+            "kernels_ms_per_step": {k: v[1] / K for k, v in kern.items()}, "kernels_frac": fracs}
 
 
 def rt_scratch_gb(w, precision, K):
