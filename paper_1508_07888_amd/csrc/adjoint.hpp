@@ -488,9 +488,14 @@ __host__ __device__ __forceinline__ void floor_limit_adj(double n, double fx, do
     if (floored) an = 0.0;
 }
 
-// Kept start states of the deferred-cell chemistry adjoint, per lane.
+// Kept start states of the deferred-cell chemistry adjoint, per lane (in
+// scratch memory, 48 B each with three groups).  With at least as many as a
+// subcycle has substeps every reverse substep restarts from its own start
+// state and the second forward pass is not needed; the 256^3 benchmark's
+// longest subcycles take ~100 substeps (0.51 ms per reverse step for this
+// pass with 128, 0.72 with 64, 0.89 with 32).
 #ifndef EMMA_ADJ_KEPT
-#define EMMA_ADJ_KEPT 32
+#define EMMA_ADJ_KEPT 128
 #endif
 
 // The chemistry adjoint of cell i (and the reverse of the floor and limiter
