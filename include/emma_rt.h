@@ -106,7 +106,7 @@ typedef struct {
        by default.  Both faces of an axis are periodic or neither. */
     int32_t bc[6];
     int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL runs on the split
-                                   and reference paths (not fused), without adjoint */
+                                   and reference paths (not fused), adjoint included */
     int32_t reserved;           /* 0 */
     double inflow[6];           /* photons cm^-2 s^-1 through each INFLOW face, >= 0 */
 } emma_rt_config;
@@ -232,8 +232,9 @@ int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double 
  * cells took more than one chemistry substep); then the steps are reversed
  * from the last.  The call uses a second stream of its own beside the
  * context's stream and joins it before returning (all its work is ordered
- * after earlier work on the context's stream).  Every boundary kind is differentiated (an inflow face's beam is a
- * constant); the HLL flux is not (EINVAL).  Returns OK, EINVAL or EHIP. */
+ * after earlier work on the context's stream).  Every boundary kind is
+ * differentiated (an inflow face's beam is a constant); so is the HLL flux
+ * (its signal speeds included).  Returns OK, EINVAL or EHIP. */
 int emma_rt_step_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
                          const double *x0, const double *T0, const double *n_H,
                          const int64_t *src_cell, const double *src_rate, int32_t n_src,

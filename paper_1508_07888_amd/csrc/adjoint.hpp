@@ -12,6 +12,8 @@
 //   k_transport_adj  gather form (no atomics), z-marching columns: the
 //                    transpose of the radius-1 stencil with the closure
 //                    Jacobian dP/d(N, F).
+//   k_transport_adj_hll  the same for the HLL flux with M1 wave speeds:
+//                    transposed face Jacobians, speed derivatives included.
 //   k_src_grad       dL/d(source rate) = sum_g frac_g / dx^3 dL/dS_g(host cell).
 #pragma once
 
@@ -857,6 +859,214 @@ __global__ __launch_bounds__(256, EMMA_ADJ_TRANSPORT_WAVES) void k_transport_adj
             here[q] = above[q];
         }
     }
+}
+
+// ---------------------------------------------------- HLL transport adjoint
+// Speeds of one state along axis d (m1_speeds in double) and their gradients
+// with respect to (N, F_x, F_y, F_z).  f = F_d/(c N) clipped to [-1, 1], 0
+// for N <= 0; where the clip or N <= 0 decides f, the gradients are zero
+// (the same selections as the oracle's min/max).  With s = sqrt(4 - 3 f^2),
+// ds/df = -3 f/s, w = 2 sqrt(3) (1 - f)(1 + f)/(1 + s) and
+// lambda-+ = c (f -+ w)/s: dlambda-+/df = c ((1 -+ w') s - (f -+ w) s')/s^2.
+struct SpeedJac {
+    double lmin, lmax;
+    double gmin[4], gmax[4];
+};
+
+__device__ inline SpeedJac speed_jac(const double (&u)[4], int d, double c) {
+    SpeedJac r{0.0, 0.0, {0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    const double N = u[0];
+    double f = 0.0;
+    bool free_f = false;
+    if (N > 0.0) {
+        const double raw = u[1 + d] / (c * N);
+        f = raw < 1.0 ? raw : 1.0;
+        f = -1.0 < f ? f : -1.0;
+        free_f = raw < 1.0 && -1.0 < raw;
+    }
+    // reciprocals to about 1 ulp: the speeds only weigh gradients here (the
+    // selections above and in the face use them as well, like the forward's
+    // own single-precision or FP64 speeds, and differ only at ties)
+    const double s = sqrt(4.0 - 3.0 * f * f);
+    const double is = recip_fp64(s), i1s = recip_fp64(1.0 + s);
+    const double w = 3.4641016151377544 * (1.0 - f) * (1.0 + f) * i1s;
+    r.lmin = c * (f - w) * is;
+    r.lmax = c * (f + w) * is;
+    if (free_f) {
+        const double ds = -3.0 * f * is;
+        const double dw = 3.4641016151377544 * (-2.0 * f * (1.0 + s) - (1.0 - f * f) * ds) * i1s * i1s;
+        const double dmin = c * ((1.0 - dw) * s - (f - w) * ds) * is * is;
+        const double dmax = c * ((1.0 + dw) * s - (f + w) * ds) * is * is;
+        const double icn = recip_fp64(c * N);
+        const double dfdN = -f * recip_fp64(N), dfdF = icn;
+        r.gmin[0] = dmin * dfdN;
+        r.gmin[1 + d] = dmin * dfdF;
+        r.gmax[0] = dmax * dfdN;
+        r.gmax[1 + d] = dmax * dfdF;
+    }
+    return r;
+}
+
+// One state's part of an HLL face along axis d: the state, its flux
+// Ft_d = (F_d, c^2 P_.d) and its speeds (with their gradients when the
+// state's own transpose is wanted).
+struct SideData {
+    double u[4], ft[4];
+    SpeedJac sj;
+};
+
+__device__ inline SideData side_data(const double (&u)[4], int d, double c) {
+    SideData sd;
+    double P[6];
+    m1_pressure<double>(u[0], u[1], u[2], u[3], c, P);
+    const int i0 = d == 0 ? 0 : (d == 1 ? 1 : 2), i1 = d == 0 ? 1 : (d == 1 ? 3 : 4),
+              i2 = d == 0 ? 2 : (d == 1 ? 4 : 5);
+    const double cc = c * c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sd.u[q] = u[q];
+    sd.ft[0] = u[1 + d];
+    sd.ft[1] = cc * P[i0];
+    sd.ft[2] = cc * P[i1];
+    sd.ft[3] = cc * P[i2];
+    sd.sj = speed_jac(u, d, c);
+    return sd;
+}
+
+// Transpose of the HLL face flux along axis d,
+//   Phi = (a+ Ft(U_L) - a- Ft(U_R) + a+ a- (U_R - U_L)) / (a+ - a-),
+// a- = min(0, lambda-_L, lambda-_R), a+ = max(0, lambda+_L, lambda+_R), for
+// v = dL/dPhi, on one side (ME: the left state when ME_L):
+//   (dPhi/dU_L)^T v = [a+ M_L^T v - a+ a- v + (v.(Ft_L + a- dU - Phi)) grad a+
+//                      + (v.(a+ dU - Ft_R + Phi)) grad a-] / (a+ - a-),
+//   (dPhi/dU_R)^T v = [-a- M_R^T v + a+ a- v + the same two terms] / (a+ - a-),
+// dU = U_R - U_L, M = dFt_d/dU (J: that side's closure Jacobian); a speed's
+// gradient term goes to the side whose speed the min/max selected (ties to
+// the left state, none when the bound is 0).
+template <bool ME_L>
+__device__ inline void hll_face_adj_side(const SideData &me, const ClosureJac &J, const SideData &other, int d,
+                                         double c, const double (&v)[4], double (&o)[4]) {
+    const SideData &L = ME_L ? me : other;
+    const SideData &R = ME_L ? other : me;
+    const bool minR = R.sj.lmin < L.sj.lmin;
+    const double m = minR ? R.sj.lmin : L.sj.lmin;
+    const bool am0 = !(m < 0.0);
+    const double am = am0 ? 0.0 : m;
+    const bool maxR = L.sj.lmax < R.sj.lmax;
+    const double M = maxR ? R.sj.lmax : L.sj.lmax;
+    const bool ap0 = !(0.0 < M);
+    const double ap = ap0 ? 0.0 : M;
+    const double iD = recip_fp64(ap - am);
+    double cp = 0.0, cm = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double du = R.u[q] - L.u[q];
+        const double phi = (ap * L.ft[q] - am * R.ft[q] + ap * am * du) * iD;
+        cp += v[q] * (L.ft[q] + am * du - phi);
+        cm += v[q] * (ap * du - R.ft[q] + phi);
+    }
+    double mm[4];
+    flux_jac_t(J, d, c, v, mm);
+    // the selected speeds' gradients count only when they are this side's
+    const bool myp = !ap0 && (maxR != ME_L), mym = !am0 && (minR != ME_L);
+    const double kp = myp ? cp * iD : 0.0, km = mym ? cm * iD : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double lin = ME_L ? (ap * mm[q] - ap * am * v[q]) : (ap * am * v[q] - am * mm[q]);
+        o[q] = lin * iD + kp * me.sj.gmax[q] + km * me.sj.gmin[q];
+    }
+}
+
+// Transpose of the transport step with the HLL flux (gather form, one thread
+// per cell and group, blockIdx.y = group), one launch per axis D: U*_i =
+// U_i + lam sum_d (Phi_{i-1/2} - Phi_{i+1/2}), so with g = dL/dU*, dL/dU_i =
+// g_i + the transposed face Jacobians of cell i's faces, its own side,
+// applied to dL/dPhi = lam (g_right - g_left); at a non-periodic face only
+// the cell inside is updated (-lam g_i across its plus face, lam g_i across
+// its minus face), and the ghost's side maps back through ghost = U_i
+// (transmissive), U_i with F_d reversed (reflective) or a constant (inflow).
+// The x launch writes g_i plus its two faces' terms to (gN, gF), the y and z
+// launches add theirs.  The cell's own face data along D is computed once.
+template <typename S, int D>
+__global__ __launch_bounds__(256) void k_transport_adj_hll(const S *__restrict__ N, const S *__restrict__ F,
+                                                           const S *__restrict__ gU, S *__restrict__ gN,
+                                                           S *__restrict__ gF, Grid gr, double c, double lam,
+                                                           Bounds<S> bnd) {
+    const int g = blockIdx.y;
+    const int64_t V = gr.V;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const int x = (int)(i % gr.nx), y = (int)((i / gr.nx) % gr.ny), z = (int)(i / ((int64_t)gr.nx * gr.ny));
+    const S *__restrict__ Ng = N + (int64_t)g * V;
+    const S *__restrict__ Fg = F + (int64_t)(3 * g) * V;
+    const S *__restrict__ gUg = gU + (int64_t)(4 * g) * V;
+    S *__restrict__ gNg = gN + (int64_t)g * V;
+    S *__restrict__ gFg = gF + (int64_t)(3 * g) * V;
+    const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
+    const double u[4] = {(double)Ng[i], (double)Fg[i], (double)Fg[V + i], (double)Fg[2 * V + i]};
+    double gi[4], out[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) gi[q] = (double)gUg[(int64_t)q * V + i];
+    if (D == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] = gi[q];
+    } else {
+        out[0] = (double)gNg[i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[1 + k] = (double)gFg[(int64_t)k * V + i];
+    }
+    const SideData me = side_data(u, D, c);
+    const ClosureJac Jme = closure_jac(u[0], u[1], u[2], u[3], c);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int face = nb.face[D][s];
+        const int64_t j = nb.idx[D][s];
+        double un[4], v[4];
+        if (face < 0) {
+            un[0] = (double)Ng[j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) un[1 + k] = (double)Fg[(int64_t)k * V + j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double gn = (double)gUg[(int64_t)q * V + j];
+                v[q] = s ? lam * (gn - gi[q]) : lam * (gi[q] - gn);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                un[q] = u[q];
+                v[q] = s ? -lam * gi[q] : lam * gi[q];
+            }
+            if (bnd.kind[face] == BC_REFLECTIVE) {
+                un[1 + D] = -un[1 + D];
+            } else if (bnd.kind[face] == BC_INFLOW) {
+                const double phi = (double)bnd.phi[face][g];
+                un[0] = phi / c;
+                un[1] = un[2] = un[3] = 0.0;
+                un[1 + D] = (face & 1) ? -phi : phi;
+            }
+        }
+        const SideData nbr = side_data(un, D, c);
+        double o[4];
+        // the cell is the left state across its plus face (s = 1), the right
+        // state across its minus face
+        if (s) hll_face_adj_side<true>(me, Jme, nbr, D, c, v, o);
+        else hll_face_adj_side<false>(me, Jme, nbr, D, c, v, o);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[q] += o[q];
+        if (face >= 0 && bnd.kind[face] != BC_INFLOW) {
+            // the ghost's side of the face, mapped back to the cell
+            double og[4];
+            const ClosureJac Jg = closure_jac(un[0], un[1], un[2], un[3], c);
+            if (s) hll_face_adj_side<false>(nbr, Jg, me, D, c, v, og);
+            else hll_face_adj_side<true>(nbr, Jg, me, D, c, v, og);
+            if (bnd.kind[face] == BC_REFLECTIVE) og[1 + D] = -og[1 + D];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[q] += og[q];
+        }
+    }
+    gNg[i] = (S)out[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gFg[(int64_t)k * V + i] = (S)out[1 + k];
 }
 
 // dL/d(rate of source s) += sum_g frac_g / dx^3 dL/dS_g(host cell of s).

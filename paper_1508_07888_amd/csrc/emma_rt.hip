@@ -168,8 +168,6 @@ static const char *config_error(const emma_rt_config *cfg) {
     if (cfg->flux != EMMA_RT_FLUX_GLF && cfg->flux != EMMA_RT_FLUX_HLL) return "bad flux";
     if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->path == EMMA_RT_PATH_FUSED)
         return "the HLL flux runs on the split and reference paths (not EMMA_RT_PATH_FUSED)";
-    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->adjoint_max_steps > 0)
-        return "the adjoint differentiates the GLF flux only (adjoint_max_steps must be 0 with HLL)";
     if (cfg->path != EMMA_RT_PATH_REFERENCE &&
         !tiled_supported(Grid{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz}))
         return "grid too large for the tiled kernels (V * 8 bytes >= 4 GiB): use the reference path";
@@ -878,9 +876,17 @@ static int tape_transport(emma_rt_ctx *c, const S *iN, const S *iF, S *uN, S *uF
     const int tb = 256;
     const double lam = cp.dt / c->cfg.dx;
     Timed t(c, KID_ADJ_FWD);
-    if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
-        hipLaunchKernelGGL((k_transport<G, S, false, true>), dim3((unsigned)((gr.V + tb - 1) / tb)), dim3(tb), 0,
-                           c->stream, iN, iF, uN, uF, gr, (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+    const bool hll = c->cfg.flux == EMMA_RT_FLUX_HLL;
+    const dim3 grid((unsigned)((gr.V + tb - 1) / tb));
+    if (c->cfg.path == EMMA_RT_PATH_REFERENCE && hll)
+        hipLaunchKernelGGL((k_transport<G, S, false, true, true>), grid, dim3(tb), 0, c->stream, iN, iF, uN, uF, gr,
+                           (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+    else if (c->cfg.path == EMMA_RT_PATH_REFERENCE)
+        hipLaunchKernelGGL((k_transport<G, S, false, true>), grid, dim3(tb), 0, c->stream, iN, iF, uN, uF, gr,
+                           (S)c->cfg.c_red, (S)lam, c->cnt, bounds_of<S>(c));
+    else if (hll)
+        launch_transport_tiled_hll<G, S, false>(c->stream, iN, iF, uN, uF, gr, cp, lam, c->cnt, bounds_of<S>(c),
+                                                true);
     else
         launch_transport_tiled<G, S, false>(c->stream, iN, iF, uN, uF, gr, cp, lam, c->cnt, bounds_of<S>(c), true);
     return check_launch(c, "transport (tape)");
@@ -1026,10 +1032,21 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
         if (int e = check_launch(c, "k_chem_adj_list")) return e;
         {
             Timed t(c, KID_ADJ_TRANSPORT);
-            const unsigned tiles = (unsigned)(((gr.nx + 63) / 64) * ((gr.ny + 3) / 4) *
-                                              ((gr.nz + kAdjLZ - 1) / kAdjLZ));
-            hipLaunchKernelGGL((k_transport_adj<S>), dim3(tiles, G), dim3(tb), 0, c->stream, tN(s), tF(s),
-                               (S *)c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+            if (c->cfg.flux == EMMA_RT_FLUX_HLL) {
+                const dim3 grid((unsigned)((V + tb - 1) / tb), G);
+                S *gUs = (S *)c->adj.gU;
+                hipLaunchKernelGGL((k_transport_adj_hll<S, 0>), grid, dim3(tb), 0, c->stream, tN(s), tF(s), gUs, gN,
+                                   gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+                hipLaunchKernelGGL((k_transport_adj_hll<S, 1>), grid, dim3(tb), 0, c->stream, tN(s), tF(s), gUs, gN,
+                                   gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+                hipLaunchKernelGGL((k_transport_adj_hll<S, 2>), grid, dim3(tb), 0, c->stream, tN(s), tF(s), gUs, gN,
+                                   gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+            } else {
+                const unsigned tiles = (unsigned)(((gr.nx + 63) / 64) * ((gr.ny + 3) / 4) *
+                                                  ((gr.nz + kAdjLZ - 1) / kAdjLZ));
+                hipLaunchKernelGGL((k_transport_adj<S>), dim3(tiles, G), dim3(tb), 0, c->stream, tN(s), tF(s),
+                                   (S *)c->adj.gU, gN, gF, gr, c->cfg.c_red, lam, bounds_of<S>(c));
+            }
         }
         if (int e = check_launch(c, "k_transport_adj")) return e;
     }

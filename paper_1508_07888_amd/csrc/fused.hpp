@@ -333,10 +333,12 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
             R fx = cur.fx + lam * ((fxl.fx - fxr.fx) + (fyl.fx - fyr.fx) + (flo.fx - fup.fx));
             R fy = cur.fy + lam * ((fxl.fy - fxr.fy) + (fyl.fy - fyr.fy) + (flo.fy - fup.fy));
             R fz = cur.fz + lam * ((fxl.fz - fxr.fz) + (fyl.fz - fyr.fz) + (flo.fz - fup.fz));
-            const int taken = floor_limit_fwd(n, fx, fy, fz, c);
-            if (active) {
-                nneg += taken & 1;
-                nlim += taken >> 1;
+            if (!a.nolimit) {
+                const int taken = floor_limit_fwd(n, fx, fy, fz, c);
+                if (active) {
+                    nneg += taken & 1;
+                    nlim += taken >> 1;
+                }
             }
             us = Vec4<R>{n, fx, fy, fz};
         }
@@ -728,7 +730,7 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
 template <int G, typename S, bool DIAG>
 inline int launch_transport_tiled_hll(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
                                       const ChemParams &cp, double lam, unsigned long long *cnt,
-                                      const Bounds<S> &bnd) {
+                                      const Bounds<S> &bnd, bool nolimit = false) {
     constexpr int TY = 4;
     const int LZ = pick_lz(gr, TY);
     for (int g = 0; g < G; ++g) {
@@ -737,6 +739,7 @@ inline int launch_transport_tiled_hll(hipStream_t st, const S *iN, const S *iF, 
         TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
                                         oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
                                         GroupConsts{}, cp, lam, cnt, LZ, WorkList{}, TY, bg);
+        a.nolimit = nolimit ? 1 : 0;
         const int nb = a.ntx * a.nty * a.ntz;
         if (gr.nx % kTX == 0 && gr.ny % TY == 0)
             hipLaunchKernelGGL((k_tiled_hll<S, DIAG, TY, true>), dim3(nb), dim3(kTX * TY), 0, st, a);

@@ -231,13 +231,14 @@ def test_checkpoint_segmentation_does_not_change_the_gradient():
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
 
 
-def test_mixed_precision_adjoint_close_to_fp64():
+@pytest.mark.parametrize("flux", ["glf", "hll"])
+def test_mixed_precision_adjoint_close_to_fp64(flux):
     from paper_1508_07888_amd import RTStep
     w = E.make_workload("adjoint64", n=24)
     G, shape = w["G"], w["shape"]
     res = {}
     for precision in ("fp64", "mixed"):
-        rt = _rt(shape, G, w["dx"], w["c_red"], 5, precision=precision)
+        rt = _rt(shape, G, w["dx"], w["c_red"], 5, precision=precision, flux=flux)
         fdt = rt.dtype
         n0 = to_dev(w["n0"]).requires_grad_(True)
         rates = to_dev(w["src_rate"]).requires_grad_(True)
@@ -248,7 +249,7 @@ def test_mixed_precision_adjoint_close_to_fp64():
         rt.close()
     for a, b in zip(res["mixed"], res["fp64"]):
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
-        print(f"mixed vs fp64 gradient: normwise {err:.2e}", flush=True)
+        print(f"{flux}: mixed vs fp64 gradient: normwise {err:.2e}", flush=True)
         assert err <= 1e-3
 
 

@@ -1,7 +1,8 @@
 """Global boundaries (transmissive, reflective, inflow faces) and the HLL
 flux on the GPU, through the C ABI, against the oracle; the adjoint with
-boundaries against the oracle's dual-number tangent; and the mirror symmetry
-of a reflective octant on the device itself.
+boundaries, and the adjoint of the HLL flux, against the oracle's
+dual-number tangent; and the mirror symmetry of a reflective octant on the
+device itself.
 
 Tolerances as in the periodic parity tests: FP64 1e-12 normwise; mixed 1e-4
 on N and F, 1e-6 absolute on x_HII, 1e-3 on T; dot products 1e-9.
@@ -130,6 +131,70 @@ def test_adjoint_with_boundaries_dot_product(name):
     rhs = sum(parts)
     scale = sum(abs(p) for p in parts)
     print(f"{name}: <w,Jv> {lhs:.14e} <J^T w,v> {rhs:.14e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-9 * max(scale, abs(lhs))
+    rt.close()
+
+
+@pytest.mark.parametrize("path", ["split", "reference"])
+@pytest.mark.parametrize("name,edge", [("periodic", False), ("periodic", True), ("transmissive", False),
+                                       ("reflective", True), ("inflow_x", False), ("inflow_yz", True),
+                                       ("mixed_kinds", False), ("thin", True)])
+def test_hll_adjoint_dot_product(name, edge, path):
+    # The adjoint of the HLL flux with M1 wave speeds (speed derivatives,
+    # the min/max selections of a+ and a-, ghost terms) against the oracle's
+    # dual-number tangent of the same flux.  edge: one step from inputs that
+    # make the closure clip, the speed clip, the floor and the limiter fire
+    # by a margin, as in the periodic test of them: 15 % of the cells with
+    # |F| = (1.05..1.5) c N, 5 % dark, 5 % with N < 0 (a cell limited to
+    # f = 1 sits on the closure's kink at the next step, where the two
+    # implementations may take different sides to rounding).
+    from paper_1508_07888_amd import EmmaRT
+    k = _case("reflective" if name == "periodic" else name, 24)
+    if name == "periodic":
+        k["bc"], k["inflow"] = None, None
+    shape = CASES["reflective" if name == "periodic" else name][0]
+    G, steps = k["G"], (1 if edge else 3)
+    N, F, x, T, n0 = E.random_state(shape, G, k["c"], seed=24, n_scale=1e-2, f_max=0.6, p_full=0.0, p_dark=0.0)
+    rng = np.random.default_rng(6)
+    if edge:
+        c = k["c"]
+        hi = rng.random(N.shape) < 0.15
+        F = np.where(hi[:, None], F / np.maximum(np.linalg.norm(F, axis=1, keepdims=True), 1e-300)
+                     * c * N[:, None] * rng.uniform(1.05, 1.5, N.shape)[:, None], F)
+        dark = (rng.random(N.shape) < 0.05) & ~hi
+        N[dark] = 0.0
+        F[np.broadcast_to(dark[:, None], F.shape)] = 0.0
+        neg = (rng.random(N.shape) < 0.05) & ~hi & ~dark
+        N[neg] = -0.3 * N[neg]
+    dN = N * rng.standard_normal(N.shape)
+    dF = F * rng.standard_normal(F.shape)
+    dxh = x * (1 - x) * rng.standard_normal(x.shape)
+    dT = T * rng.standard_normal(T.shape)
+    dn0 = n0 * rng.standard_normal(n0.shape)
+    dr = k["rates"] * rng.standard_normal(4)
+    g = groups_for(G)
+    kw = dict(dx=k["dx"], c_red=k["c"], dt=k["dt"], n_steps=steps, groups=g, bc=k["bc"], inflow=k["inflow"],
+              flux="hll")
+    (oN, oF, ox, oT), (tN, tF, tx, tT), _ = oracle.run_tangent(N, F, x, T, n0, k["cells"], k["rates"], dN, dF,
+                                                               dxh, dT, dn0, dr, **kw)
+    wN = rng.standard_normal(N.shape) / np.abs(oN).max()
+    wF = rng.standard_normal(F.shape) / np.abs(oF).max()
+    wx = rng.standard_normal(x.shape)
+    wT = rng.standard_normal(T.shape) / np.abs(oT).max()
+    lhs = (wN * tN).sum() + (wF * tF).sum() + (wx * tx).sum() + (wT * tT).sum()
+    rt = EmmaRT(shape, G, k["dx"], k["c"], precision="fp64", groups=g, adjoint_max_steps=steps, device=DEV,
+                bc=k["bc"], inflow=k["inflow"], flux="hll", path=path)
+    gN, gF, gx, gT = to_dev(wN), to_dev(wF), to_dev(wx), to_dev(wT)
+    g_n0 = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    g_rate = torch.zeros(4, dtype=torch.float64, device=DEV)
+    rt.step_adjoint(to_dev(N), to_dev(F), to_dev(x), to_dev(T), to_dev(n0), to_dev(k["cells"], torch.int64),
+                    to_dev(k["rates"]), k["dt"], steps, gN, gF, gx, gT, g_n0, g_rate)
+    torch.cuda.synchronize()
+    parts = [(gN.cpu().numpy() * dN).sum(), (gF.cpu().numpy() * dF).sum(), (gx.cpu().numpy() * dxh).sum(),
+             (gT.cpu().numpy() * dT).sum(), (g_n0.cpu().numpy() * dn0).sum(), (g_rate.cpu().numpy() * dr).sum()]
+    rhs = sum(parts)
+    scale = sum(abs(p) for p in parts)
+    print(f"hll {name} edge={edge} {path}: <w,Jv> {lhs:.14e} <J^T w,v> {rhs:.14e}", flush=True)
     assert abs(lhs - rhs) <= 1e-9 * max(scale, abs(lhs))
     rt.close()
 
