@@ -348,7 +348,7 @@ def run_variants(w, steps=10, reps=3):
     precision, `steps` steps from the initial state, median of `reps` calls
     after one warm-up step), next to the default split path over the same
     steps: the fused and reference paths, the HLL flux with M1 wave speeds
-    (reference and split paths), open boundaries with a planar inflow beam, the case-A
+    (reference, split and fused paths), open boundaries with a planar inflow beam, the case-A
     chemistry with recombination photons, and static refinement (chemistry on
     the 2^3 children of the 4096 densest cells, emma_rt_step_crta)."""
     import numpy as np
@@ -363,6 +363,7 @@ def run_variants(w, steps=10, reps=3):
         "reference_glf": dict(path="reference"),
         "reference_hll": dict(path="reference", flux="hll"),
         "split_hll": dict(flux="hll"),
+        "fused_hll": dict(path="fused", flux="hll"),
         "open_boundaries": dict(bc=["transmissive", "transmissive", "reflective", "reflective", "inflow",
                                     "transmissive"], inflow=[0, 0, 0, 0, beam, 0]),
         "case_a": dict(otsa=False),

@@ -105,8 +105,9 @@ typedef struct {
     /* Faces in the order x-, x+, y-, y+, z-, z+; emma_rt_bc values, 0 (periodic)
        by default.  Both faces of an axis are periodic or neither. */
     int32_t bc[6];
-    int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL runs on the split
-                                   and reference paths (not fused), adjoint included */
+    int32_t flux;               /* emma_rt_flux; EMMA_RT_FLUX_HLL runs on every path
+                                   (fused: one thread per cell, transport then
+                                   chemistry), adjoint included */
     int32_t reserved;           /* 0 */
     double inflow[6];           /* photons cm^-2 s^-1 through each INFLOW face, >= 0 */
 } emma_rt_config;
@@ -203,9 +204,10 @@ int emma_rt_step_noalloc(const emma_rt_config *cfg, void *hip_stream, void *N, v
  *   n_fine          device double [n_ref][ratio^3], read only
  * Child sources have density rate * src_frac / (dx / ratio)^3.  The transport
  * uses the split path's tiled kernel (fused and split paths; the tiled HLL
- * kernel with EMMA_RT_FLUX_HLL) or the reference kernel (reference path).  Entries of ref_cell outside the grid or repeated,
- * and source children outside 0..ratio^3-1, are ignored and reported as
- * EINVAL when diag is given.  No adjoint.  Returns as emma_rt_step, and EINVAL
+ * kernel with EMMA_RT_FLUX_HLL) or the reference kernel (reference path).
+ * Entries of ref_cell outside the grid or repeated, and source children
+ * outside 0..ratio^3-1, are ignored and reported as EINVAL when diag is
+ * given.  No adjoint.  Returns as emma_rt_step, and EINVAL
  * for ratio not 2 or 4 or NULL arrays with n_ref > 0. */
 int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
                       const double *n_H, const int64_t *src_cell, const double *src_rate,

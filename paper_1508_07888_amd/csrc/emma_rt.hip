@@ -166,8 +166,6 @@ static const char *config_error(const emma_rt_config *cfg) {
     for (int f = 0; f < 6; ++f)
         if (!(cfg->inflow[f] >= 0) || !isfinite(cfg->inflow[f])) return "inflow must be finite and >= 0";
     if (cfg->flux != EMMA_RT_FLUX_GLF && cfg->flux != EMMA_RT_FLUX_HLL) return "bad flux";
-    if (cfg->flux == EMMA_RT_FLUX_HLL && cfg->path == EMMA_RT_PATH_FUSED)
-        return "the HLL flux runs on the split and reference paths (not EMMA_RT_PATH_FUSED)";
     if (cfg->path != EMMA_RT_PATH_REFERENCE &&
         !tiled_supported(Grid{cfg->nx, cfg->ny, cfg->nz, (int64_t)cfg->nx * cfg->ny * cfg->nz}))
         return "grid too large for the tiled kernels (V * 8 bytes >= 4 GiB): use the reference path";
@@ -446,6 +444,23 @@ static int run_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const dou
             S *iN = even ? N : Ns, *iF = even ? F : Fs;
             S *oN = even ? Ns : N, *oF = even ? Fs : F;
             if (int e = reset_worklist(c)) return e;
+            if (c->cfg.flux == EMMA_RT_FLUX_HLL) {
+                // the HLL flux: one thread per cell, transport then chemistry
+                {
+                    Timed t(c, KID_FUSED);
+                    if (cp.otsa && !cp.isothermal)
+                        hipLaunchKernelGGL((k_step_cell<G, S, DIAG, true>), dim3(nblk), dim3(tb), 0, c->stream, iN,
+                                           iF, oN, oF, x, T, n0, gr, cr, lam, src, gc, cp, c->cnt, wl,
+                                           bounds_of<S>(c));
+                    else
+                        hipLaunchKernelGGL((k_step_cell<G, S, DIAG, false>), dim3(nblk), dim3(tb), 0, c->stream, iN,
+                                           iF, oN, oF, x, T, n0, gr, cr, lam, src, gc, cp, c->cnt, wl,
+                                           bounds_of<S>(c));
+                }
+                if (int e = check_launch(c, "k_step_cell")) return e;
+                if (int e = launch_chem_list<G, S, DIAG>(c, oN, oF, oN, oF, x, T, n0, src, gc, cp)) return e;
+                continue;
+            }
             int e;
             // single precision: the kernel with transport and chemistry waves
             // (step_ws.hpp); the FP64 state needs twice its LDS, so FP64 keeps

@@ -339,6 +339,64 @@ __device__ inline void hll(R NL, const R FL[3], const R PL[6], R NR, const R FR[
         out[1 + k] = (ap * cc * PL[col[k][d]] - am * cc * PR[col[k][d]] + pm * (FR[k] - FL[k])) * inv;
 }
 
+// The transport update of one cell (all groups) from the state (N, F):
+// U*_i = U_i + lam sum_d (flux(i - 1/2) - flux(i + 1/2)), the flux of eq.
+// (e:glf) or, with HLLF, the HLL flux; then, unless NOLIMIT, the floor and
+// the limiter (counted in nlim, nneg).
+template <int G, typename R, bool NOLIMIT, bool HLLF>
+__device__ inline void cell_transport(const R *__restrict__ N, const R *__restrict__ F, const Grid &gr, R c,
+                                      R lam, const Bounds<R> &bnd, int64_t i, R (&us)[G][4], int64_t &nlim,
+                                      int64_t &nneg) {
+    const int x = (int)(i % gr.nx);
+    const int y = (int)((i / gr.nx) % gr.ny);
+    const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
+    const int64_t V = gr.V;
+    const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const R *Ng = N + (int64_t)g * V;
+        const R *Fg = F + (int64_t)g * 3 * V;
+        const R Ni = Ng[i];
+        const R Fi[3] = {Fg[i], Fg[V + i], Fg[2 * V + i]};
+        R Pi[6];
+        m1_pressure(Ni, Fi[0], Fi[1], Fi[2], c, Pi);
+        R acc[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int64_t im = nb.idx[d][0], ip = nb.idx[d][1];
+            R Nm = Ng[im], Np = Ng[ip];
+            R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
+            R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
+            if (nb.face[d][0] >= 0) ghost(bnd, nb.face[d][0], g, c, Nm, Fm);
+            if (nb.face[d][1] >= 0) ghost(bnd, nb.face[d][1], g, c, Np, Fp);
+            R Pm[6], Pp[6];
+            m1_pressure(Nm, Fm[0], Fm[1], Fm[2], c, Pm);
+            m1_pressure(Np, Fp[0], Fp[1], Fp[2], c, Pp);
+            R lo[4], hi[4];
+            if (HLLF) {
+                hll(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
+                hll(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+            } else {
+                glf(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
+                glf(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += lo[k] - hi[k];
+        }
+        R n = Ni + lam * acc[0];
+        R f[3] = {Fi[0] + lam * acc[1], Fi[1] + lam * acc[2], Fi[2] + lam * acc[3]};
+        if (!NOLIMIT) {
+            const int taken = floor_limit_fwd(n, f[0], f[1], f[2], c);
+            nneg += taken & 1;
+            nlim += taken >> 1;
+        }
+        us[g][0] = n;
+        us[g][1] = f[0];
+        us[g][2] = f[1];
+        us[g][3] = f[2];
+    }
+}
+
 // NOLIMIT = true skips the floor and limiter (the adjoint needs the values
 // before them).  HLLF selects the HLL flux instead of eq. (e:glf).
 template <int G, typename R, bool DIAG, bool NOLIMIT = false, bool HLLF = false>
@@ -346,56 +404,16 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
                                                    R *__restrict__ Ns, R *__restrict__ Fs, Grid gr,
                                                    R c, R lam, unsigned long long *cnt, Bounds<R> bnd) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = i < gr.V;
     int64_t nlim = 0, nneg = 0;
-    if (live) {
-        const int x = (int)(i % gr.nx);
-        const int y = (int)((i / gr.nx) % gr.ny);
-        const int z = (int)(i / ((int64_t)gr.nx * gr.ny));
+    if (i < gr.V) {
         const int64_t V = gr.V;
-        const Nbrs nb = neighbours(gr, bnd, i, x, y, z);
+        R us[G][4];
+        cell_transport<G, R, NOLIMIT, HLLF>(N, F, gr, c, lam, bnd, i, us, nlim, nneg);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const R *Ng = N + (int64_t)g * V;
-            const R *Fg = F + (int64_t)g * 3 * V;
-            const R Ni = Ng[i];
-            const R Fi[3] = {Fg[i], Fg[V + i], Fg[2 * V + i]};
-            R Pi[6];
-            m1_pressure(Ni, Fi[0], Fi[1], Fi[2], c, Pi);
-            R acc[4] = {R(0), R(0), R(0), R(0)};
+            Ns[(int64_t)g * V + i] = us[g][0];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const int64_t im = nb.idx[d][0], ip = nb.idx[d][1];
-                R Nm = Ng[im], Np = Ng[ip];
-                R Fm[3] = {Fg[im], Fg[V + im], Fg[2 * V + im]};
-                R Fp[3] = {Fg[ip], Fg[V + ip], Fg[2 * V + ip]};
-                if (nb.face[d][0] >= 0) ghost(bnd, nb.face[d][0], g, c, Nm, Fm);
-                if (nb.face[d][1] >= 0) ghost(bnd, nb.face[d][1], g, c, Np, Fp);
-                R Pm[6], Pp[6];
-                m1_pressure(Nm, Fm[0], Fm[1], Fm[2], c, Pm);
-                m1_pressure(Np, Fp[0], Fp[1], Fp[2], c, Pp);
-                R lo[4], hi[4];
-                if (HLLF) {
-                    hll(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
-                    hll(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
-                } else {
-                    glf(Nm, Fm, Pm, Ni, Fi, Pi, d, c, lo);
-                    glf(Ni, Fi, Pi, Np, Fp, Pp, d, c, hi);
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k) acc[k] += lo[k] - hi[k];
-            }
-            R n = Ni + lam * acc[0];
-            R f[3] = {Fi[0] + lam * acc[1], Fi[1] + lam * acc[2], Fi[2] + lam * acc[3]};
-            if (!NOLIMIT) {
-                const int taken = floor_limit_fwd(n, f[0], f[1], f[2], c);
-                nneg += taken & 1;
-                nlim += taken >> 1;
-            }
-            Ns[(int64_t)g * V + i] = n;
-            Fs[(int64_t)g * 3 * V + i] = f[0];
-            Fs[(int64_t)g * 3 * V + V + i] = f[1];
-            Fs[(int64_t)g * 3 * V + 2 * V + i] = f[2];
+            for (int k = 0; k < 3; ++k) Fs[(int64_t)(3 * g + k) * V + i] = us[g][1 + k];
         }
     }
     if (DIAG) {
@@ -702,6 +720,67 @@ __global__ __launch_bounds__(256) void k_chem_list(const S *Ns, const S *Fs, S *
         wave_count(cnt, CNT_CAP, tot.cap);
         wave_count(cnt, CNT_XCLAMP, tot.xclamp);
         wave_count_max(cnt, CNT_MAXSUB, maxsub);
+    }
+}
+
+// One-pass step of the fused path with the HLL flux: one thread per cell
+// reads its radius-1 neighbourhood of (N, F), updates its own U* (all
+// groups, the floor and the limiter), and runs the chemistry on it in the
+// same thread, writing (No, Fo) and x, T in place; a subcycle longer than
+// kChemBudgetFused substeps writes U* instead and goes to the work list,
+// which k_chem_list finishes in place.  (The tiled fused kernels split the
+// GLF flux into per-cell parts shared through LDS; the HLL flux needs both
+// sides' states and speeds at every face, which this form reads from memory.)
+template <int G, typename R, bool DIAG, bool FAST>
+__global__ __launch_bounds__(256) void k_step_cell(const R *__restrict__ N, const R *__restrict__ F,
+                                                   R *__restrict__ No, R *__restrict__ Fo, double *__restrict__ x,
+                                                   double *__restrict__ T, const double *__restrict__ n0, Grid gr,
+                                                   R c, R lam, SrcTable src, GroupConsts gc, ChemParams cp,
+                                                   unsigned long long *cnt, WorkList wl, Bounds<R> bnd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t V = gr.V;
+    int64_t nlim = 0, nneg = 0;
+    bool deferred = false, done = false;
+    ChemStats cs{0, 0, 0, 0};
+    if (i < V) {
+        R us[G][4];
+        cell_transport<G, R, false, true>(N, F, gr, c, lam, bnd, i, us, nlim, nneg);
+        double Nc[G], Pf[G], Sc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) Nc[g] = (double)us[g][0];
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        double xc = x[i], Tc = T[i];
+        cs = chem_cell_nxt<G, FAST>(gc, cp, Nc, Pf, xc, Tc, n0[i], Sc, kChemBudgetFused, &deferred);
+        if (!deferred) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                us[g][0] = (R)Nc[g];
+#pragma unroll
+                for (int k = 1; k < 4; ++k) us[g][k] = (R)((double)us[g][k] * Pf[g]);
+            }
+            x[i] = xc;
+            T[i] = Tc;
+            done = true;
+        } else {
+            cs = ChemStats{0, 0, 0, 0};  // counted by k_chem_list
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            No[(int64_t)g * V + i] = us[g][0];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fo[(int64_t)(3 * g + k) * V + i] = us[g][1 + k];
+        }
+    }
+    defer_push(wl, deferred, (uint32_t)i);
+    if (DIAG) {
+        wave_count(cnt, CNT_LIMITER, nlim);
+        wave_count(cnt, CNT_NEG, nneg);
+        wave_count(cnt, CNT_SUB, cs.substeps);
+        wave_count(cnt, CNT_ATT, cs.attempts);
+        wave_count(cnt, CNT_CAP, cs.cap);
+        wave_count(cnt, CNT_XCLAMP, cs.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, cs.substeps);
+        wave_hist(cnt, done, cs.substeps);
     }
 }
 

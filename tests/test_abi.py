@@ -75,7 +75,7 @@ def _cfg(**kw):
     (dict(bc=(ctypes.c_int32 * 6)(1, 0, 0, 0, 0, 0)), "periodic or neither"),
     (dict(bc=(ctypes.c_int32 * 6)(0, 0, 4, 4, 0, 0)), "bc values"),
     (dict(inflow=(ctypes.c_double * 6)(0, 0, 0, -1.0, 0, 0)), "inflow"),
-    (dict(flux=2), "flux"), (dict(flux=1, path=1), "not EMMA_RT_PATH_FUSED"),
+    (dict(flux=2), "flux"),
 ])
 def test_init_rejects_bad_config(kw, msg):
     L = _lib.load()

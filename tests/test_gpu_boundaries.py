@@ -76,7 +76,7 @@ def test_boundaries_match_oracle(name, precision, path):
         assert d["substeps"] == oc["substeps"] and d["limiter_hits"] == oc["limiter"]
 
 
-@pytest.mark.parametrize("path", ["reference", "split"])
+@pytest.mark.parametrize("path", ["reference", "split", "fused"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["transmissive", "inflow_x", "inflow_yz", "thin", "periodic", "reflective",
                                   "mixed_kinds", "whole_tiles"])
