@@ -51,6 +51,11 @@ def lib():
         L.oracle_run_crta.argtypes = [_ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                                       _lp, _dp, _ip, ctypes.c_int, ctypes.c_int, _lp, ctypes.c_int,
                                       _dp, _dp, _dp, _lp]
+        L.oracle_run_crta_tangent.restype = ctypes.c_int
+        L.oracle_run_crta_tangent.argtypes = [_ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                              _lp, _dp, _ip, ctypes.c_int, ctypes.c_int, _lp, ctypes.c_int,
+                                              _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                              _lp]
         L.oracle_transport.restype = ctypes.c_int
         L.oracle_transport.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _lp]
         L.oracle_chem_cell.restype = ctypes.c_int
@@ -189,6 +194,38 @@ def run_crta(N, F, x, T, n0, src_cell, src_rate, src_child, ref_cell, ratio, x_f
     if rc != 0:
         raise ValueError("oracle_run_crta rejected its arguments")
     return N, F, x, T, xf, Tf, _counters(cnt)
+
+
+def run_crta_tangent(N, F, x, T, n0, src_cell, src_rate, src_child, ref_cell, ratio, x_fine, T_fine, n_fine,
+                     dN, dF, dxh, dT, dn0, drate, dxf, dTf, dnf, *, dx, c_red, dt, n_steps, groups, otsa=1,
+                     isothermal=0, max_substeps=100000, bc=None, inflow=None, flux="glf"):
+    """run_crta carried in dual numbers: returns the end state
+    (N, F, x, T, x_fine, T_fine), its directional derivative along the given
+    directions of the coarse state, the children's state and n_fine, and the
+    source rates, and the counters."""
+    N = _f64(N).copy(); F = _f64(F).copy(); x = _f64(x).copy(); T = _f64(T).copy()
+    n0 = _f64(n0)
+    xf = _f64(x_fine).copy(); Tf = _f64(T_fine).copy(); nf = _f64(n_fine)
+    dN = _f64(dN).copy(); dF = _f64(dF).copy(); dxh = _f64(dxh).copy(); dT = _f64(dT).copy()
+    dn0 = _f64(dn0); dr = _f64(drate)
+    dxf = _f64(dxf).copy(); dTf = _f64(dTf).copy(); dnf = _f64(dnf)
+    G = N.shape[0]
+    ints, dbls, gr = _pack(n0.shape, G, dx, c_red, dt, groups, otsa, isothermal, max_substeps,
+                           bc, inflow, flux)
+    sc = np.ascontiguousarray(src_cell, dtype=np.int64)
+    sr = _f64(src_rate)
+    ch = np.ascontiguousarray(np.zeros(sc.size) if src_child is None else src_child, dtype=np.int32)
+    rc_ = np.ascontiguousarray(ref_cell, dtype=np.int64)
+    cnt = np.zeros(7, dtype=np.int64)
+    rc = lib().oracle_run_crta_tangent(ints.ctypes.data_as(_ip), _d(dbls), _d(gr), int(n_steps),
+                                       _d(N), _d(F), _d(x), _d(T), _d(n0), sc.ctypes.data_as(_lp), _d(sr),
+                                       ch.ctypes.data_as(_ip), int(sc.size), int(rc_.size),
+                                       rc_.ctypes.data_as(_lp), int(ratio), _d(xf), _d(Tf), _d(nf),
+                                       _d(dN), _d(dF), _d(dxh), _d(dT), _d(dn0), _d(dr), _d(dxf), _d(dTf),
+                                       _d(dnf), cnt.ctypes.data_as(_lp))
+    if rc != 0:
+        raise ValueError("oracle_run_crta_tangent rejected its arguments")
+    return (N, F, x, T, xf, Tf), (dN, dF, dxh, dT, dxf, dTf), _counters(cnt)
 
 
 def transport(N, F, *, dx, c_red, dt, bc=None, inflow=None, flux="glf", frac=None):

@@ -746,6 +746,74 @@ int oracle_run_crta(const int *ints, const double *dbls, const double *groups, i
     return 0;
 }
 
+/* R19 carried in dual numbers: the end state (coarse and children) and its
+ * directional derivative along (dN, dF, dx, dT, dn0) of the coarse state,
+ * (dxf, dTf, dnf) of the children and drate of the source rates.  Source
+ * densities as in oracle_run_crta. */
+int oracle_run_crta_tangent(const int *ints, const double *dbls, const double *groups, int n_steps,
+                            double *N, double *F, double *x, double *T, const double *n0,
+                            const int64_t *src_cell, const double *src_rate, const int *src_child, int n_src,
+                            int n_ref, const int64_t *ref_cell, int ratio, double *xf, double *Tf,
+                            const double *nf, double *dN, double *dF, double *dx_, double *dT, const double *dn0,
+                            const double *drate, double *dxf, double *dTf, const double *dnf, int64_t *counters) {
+    Params p;
+    if (!fill_params(p, ints, dbls, groups)) return -1;
+    if (ratio != 2 && ratio != 4) return -1;
+    const int64_t V = (int64_t)p.nx * p.ny * p.nz;
+    const int nc = ratio * ratio * ratio;
+    std::vector<int> which((size_t)V, -1);
+    for (int j = 0; j < n_ref; ++j) {
+        if (ref_cell[j] < 0 || ref_cell[j] >= V || which[(size_t)ref_cell[j]] >= 0) return -1;
+        which[(size_t)ref_cell[j]] = j;
+    }
+    const int G = p.G;
+    const size_t nfine = (size_t)n_ref * nc;
+    std::vector<Dual> dN_((size_t)G * V), dF_((size_t)G * 3 * V), dX(V), dTT(V), dn(V);
+    std::vector<Dual> dXf(nfine), dTf_(nfine), dNf(nfine);
+    for (int64_t i = 0; i < (int64_t)G * V; ++i) dN_[i] = Dual(N[i], dN[i]);
+    for (int64_t i = 0; i < (int64_t)G * 3 * V; ++i) dF_[i] = Dual(F[i], dF[i]);
+    for (int64_t i = 0; i < V; ++i) {
+        dX[i] = Dual(x[i], dx_[i]);
+        dTT[i] = Dual(T[i], dT[i]);
+        dn[i] = Dual(n0[i], dn0[i]);
+    }
+    for (size_t f = 0; f < nfine; ++f) {
+        dXf[f] = Dual(xf[f], dxf[f]);
+        dTf_[f] = Dual(Tf[f], dTf[f]);
+        dNf[f] = Dual(nf[f], dnf[f]);
+    }
+    std::vector<Dual> Sc((size_t)V * G, Dual(0.0)), Sf(nfine * G, Dual(0.0));
+    const double vol = p.dx * p.dx * p.dx;
+    const double hf = p.dx / ratio;
+    const double volf = hf * hf * hf;
+    for (int s = 0; s < n_src; ++s) {
+        const Dual r(src_rate[s], drate[s]);
+        const int j = which[(size_t)src_cell[s]];
+        if (j < 0) {
+            for (int g = 0; g < G; ++g) Sc[(size_t)src_cell[s] * G + g] += r * Dual(p.frac[g]) / Dual(vol);
+        } else {
+            const int c = src_child ? src_child[s] : 0;
+            if (c < 0 || c >= nc) return -1;
+            for (int g = 0; g < G; ++g) Sf[((size_t)j * nc + c) * G + g] += r * Dual(p.frac[g]) / Dual(volf);
+        }
+    }
+    Counters cnt;
+    run_crta<Dual>(p, n_steps, dN_.data(), dF_.data(), dX.data(), dTT.data(), dn.data(), Sc, n_ref, ref_cell,
+                   ratio, dXf.data(), dTf_.data(), dNf.data(), Sf, cnt);
+    for (int64_t i = 0; i < (int64_t)G * V; ++i) { N[i] = dN_[i].v; dN[i] = dN_[i].d; }
+    for (int64_t i = 0; i < (int64_t)G * 3 * V; ++i) { F[i] = dF_[i].v; dF[i] = dF_[i].d; }
+    for (int64_t i = 0; i < V; ++i) {
+        x[i] = dX[i].v; dx_[i] = dX[i].d;
+        T[i] = dTT[i].v; dT[i] = dTT[i].d;
+    }
+    for (size_t f = 0; f < nfine; ++f) {
+        xf[f] = dXf[f].v; dxf[f] = dXf[f].d;
+        Tf[f] = dTf_[f].v; dTf[f] = dTf_[f].d;
+    }
+    export_counters(cnt, counters);
+    return 0;
+}
+
 /* Transport only (eq. e:uprt with the flux of eq. e:glf), one step. */
 int oracle_transport(const int *ints, const double *dbls, const double *groups,
                      const double *N, const double *F, double *Ns, double *Fs,
