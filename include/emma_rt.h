@@ -207,8 +207,8 @@ int emma_rt_step_noalloc(const emma_rt_config *cfg, void *hip_stream, void *N, v
  * kernel with EMMA_RT_FLUX_HLL) or the reference kernel (reference path).
  * Entries of ref_cell outside the grid or repeated, and source children
  * outside 0..ratio^3-1, are ignored and reported as EINVAL when diag is
- * given.  No adjoint.  Returns as emma_rt_step, and EINVAL
- * for ratio not 2 or 4 or NULL arrays with n_ref > 0. */
+ * given.  Its adjoint is emma_rt_step_crta_adjoint.  Returns as emma_rt_step,
+ * and EINVAL for ratio not 2 or 4 or NULL arrays with n_ref > 0. */
 int emma_rt_step_crta(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
                       const double *n_H, const int64_t *src_cell, const double *src_rate,
                       const int32_t *src_child, int32_t n_src, double dt, int32_t n_steps,
@@ -243,6 +243,47 @@ int emma_rt_step_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
                          double dt, int32_t n_steps,
                          void *gN, void *gF, double *gx, double *gT,
                          double *g_nH, double *g_src_rate);
+
+/* Bytes of the device workspace emma_rt_step_crta_adjoint needs for a segment
+ * of n_steps steps: the children's x_HII and T after each step but the last,
+ * (n_steps - 1) n_ref ratio^3 16.  -1 for n_steps < 1, n_ref < 0 or ratio
+ * not 2 or 4. */
+int64_t emma_rt_crta_adjoint_work_bytes(int32_t n_steps, int32_t n_ref, int32_t ratio);
+
+/* Vector-Jacobian product of n_steps steps of emma_rt_step_crta (the coarse
+ * radiative transport approximation of Sec. 5), with the same conventions as
+ * emma_rt_step_adjoint: the derivative of the discrete map along the branches
+ * the forward run takes.
+ *   N0 ... n_steps  as emma_rt_step_adjoint, plus src_child as emma_rt_step_crta
+ *   ref_cell, n_ref, ratio, n_fine   as emma_rt_step_crta; ref_cell entries
+ *                   must lie in the grid and be distinct (else EINVAL, after
+ *                   one small device-to-host read, before the segment runs)
+ *   x_fine0, T_fine0 device double [n_ref][ratio^3], the children's state at
+ *                   the start of the segment (not modified)
+ *   work, work_bytes device workspace of at least
+ *                   emma_rt_crta_adjoint_work_bytes(n_steps, n_ref, ratio)
+ *                   bytes, 8-byte aligned, owned by the caller; NULL when
+ *                   that is 0; its contents on return are unspecified
+ *   gN ... g_src_rate as emma_rt_step_adjoint (on exit, gx and gT of refined
+ *                   cells are 0: the forward overwrites those cells' x_HII and
+ *                   T with the children's means; a source whose src_child is
+ *                   outside 0..ratio^3-1 in a refined cell gets nothing, as
+ *                   the forward ignores it)
+ *   g_x_fine, g_T_fine device double [n_ref][ratio^3]: on entry dL/d(children's
+ *                   x_HII, T at segment end), on exit dL/d(at segment start)
+ *   g_n_fine        device double [n_ref][ratio^3], dL/dn_fine is ADDED to it
+ * Needs the context's adjoint scratch (adjoint_max_steps >= n_steps); the
+ * children's part of the tape lives in work.  Returns OK, EINVAL or EHIP. */
+int emma_rt_step_crta_adjoint(emma_rt_ctx *ctx, const void *N0, const void *F0,
+                              const double *x0, const double *T0, const double *n_H,
+                              const int64_t *src_cell, const double *src_rate,
+                              const int32_t *src_child, int32_t n_src, double dt,
+                              int32_t n_steps, const int64_t *ref_cell, int32_t n_ref,
+                              int32_t ratio, const double *x_fine0, const double *T_fine0,
+                              const double *n_fine, void *work, int64_t work_bytes,
+                              void *gN, void *gF, double *gx, double *gT, double *g_nH,
+                              double *g_src_rate, double *g_x_fine, double *g_T_fine,
+                              double *g_n_fine);
 
 /* Release the context and all its device scratch.  NULL is a no-op. */
 void emma_rt_free(emma_rt_ctx *ctx);

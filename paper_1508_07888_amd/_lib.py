@@ -29,7 +29,8 @@ FLUXES = {"glf": 0, "hll": 1}
 
 EXPORTS = ("emma_rt_init", "emma_rt_step", "emma_rt_step_crta", "emma_rt_step_adjoint", "emma_rt_free",
            "emma_rt_last_error", "emma_rt_group_constants", "emma_rt_scratch_bytes",
-           "emma_rt_profile_enable", "emma_rt_profile_read", "emma_rt_step_noalloc")
+           "emma_rt_profile_enable", "emma_rt_profile_read", "emma_rt_step_noalloc",
+           "emma_rt_step_crta_adjoint", "emma_rt_crta_adjoint_work_bytes")
 NOALLOC_SCRATCH_BYTES = 128 << 20  # EMMA_RT_NOALLOC_SCRATCH_BYTES
 
 
@@ -99,6 +100,12 @@ def load():
     L.emma_rt_step_adjoint.restype = ctypes.c_int
     L.emma_rt_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                        ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.emma_rt_step_crta_adjoint.restype = ctypes.c_int
+    L.emma_rt_step_crta_adjoint.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_int32, _vp, ctypes.c_int32,
+                                            ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int64] + [_vp] * 9
+    L.emma_rt_crta_adjoint_work_bytes.restype = ctypes.c_int64
+    L.emma_rt_crta_adjoint_work_bytes.argtypes = [ctypes.c_int32] * 3
     L.emma_rt_free.restype = None
     L.emma_rt_free.argtypes = [_vp]
     L.emma_rt_last_error.restype = ctypes.c_char_p
@@ -180,6 +187,23 @@ def emma_rt_step_adjoint(ctx, N0, F0, x0, T0, n0, src_cell, src_rate, n_src, dt,
     return L.emma_rt_step_adjoint(ctx, _vp(N0), _vp(F0), _vp(x0), _vp(T0), _vp(n0), _vp(src_cell),
                                   _vp(src_rate), int(n_src), float(dt), int(n_steps), _vp(gN),
                                   _vp(gF), _vp(gx), _vp(gT), _vp(g_n0), _vp(g_rate))
+
+
+def emma_rt_crta_adjoint_work_bytes(n_steps, n_ref, ratio):
+    return load().emma_rt_crta_adjoint_work_bytes(int(n_steps), int(n_ref), int(ratio))
+
+
+def emma_rt_step_crta_adjoint(ctx, N0, F0, x0, T0, n0, src_cell, src_rate, src_child, n_src, dt, n_steps,
+                              ref_cell, n_ref, ratio, x_fine0, T_fine0, n_fine, work, work_bytes,
+                              gN, gF, gx, gT, g_n0, g_rate, g_x_fine, g_T_fine, g_n_fine):
+    """Pointers are integers (device addresses, 0 = NULL); returns the status code."""
+    L = load()
+    return L.emma_rt_step_crta_adjoint(ctx, _vp(N0), _vp(F0), _vp(x0), _vp(T0), _vp(n0), _vp(src_cell),
+                                       _vp(src_rate), _vp(src_child), int(n_src), float(dt), int(n_steps),
+                                       _vp(ref_cell), int(n_ref), int(ratio), _vp(x_fine0), _vp(T_fine0),
+                                       _vp(n_fine), _vp(work), int(work_bytes), _vp(gN), _vp(gF), _vp(gx),
+                                       _vp(gT), _vp(g_n0), _vp(g_rate), _vp(g_x_fine), _vp(g_T_fine),
+                                       _vp(g_n_fine))
 
 
 def emma_rt_free(ctx):

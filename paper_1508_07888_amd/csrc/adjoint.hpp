@@ -611,13 +611,16 @@ __global__ __launch_bounds__(EMMA_ADJ_TB, EMMA_ADJ_CHEM_WAVES) void k_chem_adj(c
                                                   const S *__restrict__ gF, double *__restrict__ gx,
                                                   double *__restrict__ gT, double *__restrict__ g_n0,
                                                   double *__restrict__ gS, S *__restrict__ gU, WorkList wl,
-                                                  const uint64_t *__restrict__ multi) {
+                                                  const uint64_t *__restrict__ multi,
+                                                  const uint32_t *__restrict__ skip) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t mw = 0;
     if (multi) mw = multi[min(i, V - 1) >> 6];  // same branch for every lane
     const bool listed = (mw >> (i & 63)) & 1ull;
+    // skip: refined cells, whose children's adjoint (k_crta_adj) takes them
+    const bool refined = skip && i < V && ((skip[i >> 5] >> (i & 31)) & 1u);
     bool deferred = false;
-    if (i < V)
+    if (i < V && !refined)
         deferred = !chem_adj_cell<G, S, FAST, -1>(i, Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, gS,
                                                   gU, 1, listed);
     defer_push(wl, deferred, (uint32_t)i);
@@ -667,6 +670,128 @@ __global__ __launch_bounds__(256, EMMA_ADJ_LIST_WAVES) void k_chem_adj_list(cons
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
         chem_adj_cell<G, S, FAST, EMMA_ADJ_KEPT>((int64_t)wl.cells[k], Ut, Ft, xs, Ts, n0, V, src, gc, cp, gN, gF,
                                                  gx, gT, g_n0, gS, gU, 0x7fffffff);
+}
+
+// Reverse of the refined-cell chemistry (the step of emma_rt_step_crta after
+// the coarse transport), one lane per child, NC consecutive lanes per parent
+// as in k_crta_fine.  Each lane replays its child's subcycle to get the
+// child's end state, forms the derivatives of the restriction (parent N, F:
+// means over the children; x: n_fine-weighted; T: (1 + x) n_fine-weighted),
+// adds them to dL/d(child's end state), runs the kept-state chemistry adjoint
+// of the child, and writes dL/d(child's start state) over (gxf, gTf), adds
+// dL/dn_fine to gnf and dL/d(rate) of its sources to g_rate.  The parent's
+// dL/dU* is the sum over its children (the same lane tree as the forward's
+// sums), taken through the reverse of the floor and the limiter; the parent's
+// own x, T do not reach the step's end state (gx, gT of the parent become 0).
+template <int G, typename S, bool FAST, int NC>
+__global__ __launch_bounds__(256) void k_crta_adj(const S *__restrict__ Ut, const S *__restrict__ Ft, int64_t V,
+                                                  const int64_t *__restrict__ ref_cell, int n_ref,
+                                                  const double *__restrict__ xfi, const double *__restrict__ Tfi,
+                                                  const double *__restrict__ nf,
+                                                  const int64_t *__restrict__ sorted_cell,
+                                                  const int32_t *__restrict__ sorted_idx,
+                                                  const double *__restrict__ rate,
+                                                  const int32_t *__restrict__ src_child, int n_src,
+                                                  GroupConsts gc, ChemParams cp, double volf,
+                                                  const S *__restrict__ gN, const S *__restrict__ gF,
+                                                  double *__restrict__ gx, double *__restrict__ gT,
+                                                  double *__restrict__ gxf, double *__restrict__ gTf,
+                                                  double *__restrict__ gnf, double *__restrict__ g_rate,
+                                                  S *__restrict__ gU) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = t / NC;
+    const int ch = (int)(t % NC);
+    const int64_t p = j < n_ref ? ref_cell[j] : -1;
+    // every lane of a parent agrees on this, so the sums stay inside live lanes
+    if (!(p >= 0 && p < V)) return;
+    const double c = cp.c;
+    double Npre[G], Fpre[G][3], Nst[G], Fst[G][3], Sc[G];
+    int taken[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        S n = Ut[(int64_t)g * V + p];
+        S f[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[k] = Ft[((int64_t)g * 3 + k) * V + p];
+        Npre[g] = (double)n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fpre[g][k] = (double)f[k];
+        taken[g] = floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)c);
+        Nst[g] = (double)n;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Fst[g][k] = (double)f[k];
+        Sc[g] = 0.0;
+    }
+    // the child's sources, as in k_crta_fine
+    const int r0 = n_src > 0 ? lower_bound_cell(sorted_cell, n_src, p) : 0;
+    for (int r = r0; r < n_src && sorted_cell[r] == p; ++r) {
+        const int s = sorted_idx[r];
+        if ((src_child ? src_child[s] : 0) == ch) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) Sc[g] += rate[s] * gc.frac[g] / volf;
+        }
+    }
+    const int64_t f = j * NC + ch;
+    const double xin = xfi[f], Tin = Tfi[f], nfc = nf[f];
+    // the child's end state (x, T) and the restriction's sums, as the forward
+    double Nc[G], Pf[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) Nc[g] = Nst[g];
+    double xo = xin, To = Tin;
+    chem_cell_nxt<G, FAST>(gc, cp, Nc, Pf, xo, To, nfc, Sc);
+    const double nsum = child_sum<NC>(nfc);
+    const double xp = child_sum<NC>(xo * (nfc / nsum));
+    const double w = (1.0 + xo) * nfc;
+    const double msum = child_sum<NC>(w);
+    const double Tp = child_sum<NC>(To * (w / msum));
+    // dL/d(parent's end state), read by every child before lane 0 rewrites it
+    const double gxp = gx[p], gTp = gT[p];
+    const double inv = 1.0 / NC;
+    double aNo[G], aFo[G][3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        aNo[g] = (double)gN[(int64_t)g * V + p] * inv;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) aFo[g][k] = (double)gF[((int64_t)g * 3 + k) * V + p] * inv;
+    }
+    // x_p = sum x n / nsum, T_p = sum T w / msum with w = (1 + x) n
+    const double dw = gTp * (To - Tp) / msum;
+    const double axo = gxf[f] + gxp * nfc / nsum + dw * nfc;
+    const double aTo = gTf[f] + gTp * w / msum;
+    const double an_restr = gxp * (xo - xp) / nsum + dw * (1.0 + xo);
+    double aN[G], aF[G][3], aS[G], ax, aT, an0;
+    chem_cell_adj<G, FAST, EMMA_ADJ_KEPT>(gc, cp, Nst, Fst, xin, Tin, nfc, Sc, aNo, aFo, axo, aTo, aN, aF, ax, aT,
+                                          an0, aS);
+    gxf[f] = ax;
+    gTf[f] = aT;
+    gnf[f] += an0 + an_restr;
+    for (int r = r0; r < n_src && sorted_cell[r] == p; ++r) {
+        const int s = sorted_idx[r];
+        if ((src_child ? src_child[s] : 0) == ch) {
+            double d = 0.0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) d += gc.frac[g] / volf * aS[g];
+            g_rate[s] += d;
+        }
+    }
+    // the parent's dL/dU*: the children's sum, then the floor and the limiter
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double an = child_sum<NC>(aN[g]);
+        double af[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) af[k] = child_sum<NC>(aF[g][k]);
+        if (ch == 0) {
+            floor_limit_adj(Npre[g], Fpre[g][0], Fpre[g][1], Fpre[g][2], c, taken[g], an, af[0], af[1], af[2]);
+            gU[(int64_t)(4 * g) * V + p] = (S)an;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gU[(int64_t)(4 * g + 1 + k) * V + p] = (S)af[k];
+        }
+    }
+    if (ch == 0) {
+        gx[p] = 0.0;
+        gT[p] = 0.0;
+    }
 }
 
 // ------------------------------------------------------- transport adjoint

@@ -793,12 +793,12 @@ static int crta_steps(emma_rt_ctx *c, S *N, S *F, double *x, double *T, const do
             Timed t(c, KID_CRTA);
             if (fast)
                 hipLaunchKernelGGL((k_crta_fine<G, S, DIAG, true, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ns, Fs,
-                                   N, F, x, T, V, ref_cell, n_ref, xf, Tf, nf, c->sorted_cell, c->sorted_idx, rate,
-                                   src_child, n_src, gc, cp, volf, c->cnt);
+                                   N, F, x, T, V, ref_cell, n_ref, xf, Tf, xf, Tf, nf, c->sorted_cell, c->sorted_idx,
+                                   rate, src_child, n_src, gc, cp, volf, c->cnt);
             else
                 hipLaunchKernelGGL((k_crta_fine<G, S, DIAG, false, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ns,
-                                   Fs, N, F, x, T, V, ref_cell, n_ref, xf, Tf, nf, c->sorted_cell, c->sorted_idx,
-                                   rate, src_child, n_src, gc, cp, volf, c->cnt);
+                                   Fs, N, F, x, T, V, ref_cell, n_ref, xf, Tf, xf, Tf, nf, c->sorted_cell,
+                                   c->sorted_idx, rate, src_child, n_src, gc, cp, volf, c->cnt);
             if (int e = check_launch(c, "k_crta_fine")) return e;
         }
     }
@@ -915,7 +915,8 @@ static int tape_transport(emma_rt_ctx *c, const S *iN, const S *iF, S *uN, S *uF
 // at load).  multi: the cells whose subcycle was not a single substep.
 template <int G, typename S>
 static int tape_chem(emma_rt_ctx *c, const S *uN, const S *uF, const double *ix, const double *iT, S *oN, S *oF,
-                     double *ox, double *oT, const double *n0, int n_src, const ChemParams &cp, uint64_t *multi) {
+                     double *ox, double *oT, const double *n0, int n_src, const ChemParams &cp, uint64_t *multi,
+                     const uint32_t *skip) {
     const GroupConsts gc = group_consts(c->cfg);
     const SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
     if (int e = reset_worklist(c)) return e;
@@ -923,18 +924,71 @@ static int tape_chem(emma_rt_ctx *c, const S *uN, const S *uF, const double *ix,
         Timed t(c, KID_CHEM);
         const int e = (cp.otsa && !cp.isothermal)
                           ? launch_chem<G, S, false, true>(c, uN, uF, oN, oF, (double *)ix, (double *)iT, ox, oT,
-                                                           n0, src, gc, cp, nullptr, multi)
+                                                           n0, src, gc, cp, skip, multi)
                           : launch_chem<G, S, false, false>(c, uN, uF, oN, oF, (double *)ix, (double *)iT, ox, oT,
-                                                            n0, src, gc, cp, nullptr, multi);
+                                                            n0, src, gc, cp, skip, multi);
         if (e) return e;
     }
     return launch_chem_cont<G, S, false>(c, uF, oN, oF, iT, ox, oT, n0, src, gc, cp, uN);
 }
 
+// The refined cells of emma_rt_step_crta_adjoint (n_ref = 0: the plain step).
+struct CrtaAdj {
+    const int64_t *ref_cell;
+    int n_ref, nc;                 // nc = ratio^3
+    const int32_t *src_child;
+    const double *xf0, *Tf0, *nf;  // children's start state, n_fine
+    double *tape;                  // [K - 1][2][n_ref nc]: children's x, T after steps 1..K-1
+    double *gxf, *gTf, *gnf;
+};
+
+template <int G, typename S, int NC>
+static int crta_adj_launch(emma_rt_ctx *c, const S *Ut, const S *Ft, const double *xfi, const double *Tfi,
+                           const double *rate, int n_src, const GroupConsts &gc, const ChemParams &cp,
+                           const CrtaAdj &ca, const S *gN, const S *gF, double *gx, double *gT, double *g_rate,
+                           S *gU) {
+    const int tb = 256;
+    const double hf = c->cfg.dx / (NC == 8 ? 2 : 4);
+    const double volf = hf * hf * hf;
+    const unsigned fblk = (unsigned)(((int64_t)ca.n_ref * NC + tb - 1) / tb);
+    if (cp.otsa && !cp.isothermal)
+        hipLaunchKernelGGL((k_crta_adj<G, S, true, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ut, Ft, c->grid.V,
+                           ca.ref_cell, ca.n_ref, xfi, Tfi, ca.nf, c->sorted_cell, c->sorted_idx, rate, ca.src_child,
+                           n_src, gc, cp, volf, gN, gF, gx, gT, ca.gxf, ca.gTf, ca.gnf, g_rate, gU);
+    else
+        hipLaunchKernelGGL((k_crta_adj<G, S, false, NC>), dim3(fblk), dim3(tb), 0, c->stream, Ut, Ft, c->grid.V,
+                           ca.ref_cell, ca.n_ref, xfi, Tfi, ca.nf, c->sorted_cell, c->sorted_idx, rate, ca.src_child,
+                           n_src, gc, cp, volf, gN, gF, gx, gT, ca.gxf, ca.gTf, ca.gnf, g_rate, gU);
+    return check_launch(c, "k_crta_adj");
+}
+
+// The refined cells' part of a tape step: the children's chemistry from the
+// transport output before the floor and the limiter, children's state slot s
+// into slot s + 1, the parents' restriction into the coarse tape slot s + 1.
+template <int G, typename S, int NC>
+static int crta_tape_launch(emma_rt_ctx *c, const S *uN, const S *uF, S *oN, S *oF, double *ox, double *oT,
+                            const double *xfi, const double *Tfi, double *xfo, double *Tfo, const double *rate,
+                            int n_src, const GroupConsts &gc, const ChemParams &cp, const CrtaAdj &ca) {
+    const int tb = 256;
+    const double hf = c->cfg.dx / (NC == 8 ? 2 : 4);
+    const double volf = hf * hf * hf;
+    const unsigned fblk = (unsigned)(((int64_t)ca.n_ref * NC + tb - 1) / tb);
+    if (cp.otsa && !cp.isothermal)
+        hipLaunchKernelGGL((k_crta_fine<G, S, false, true, NC, true>), dim3(fblk), dim3(tb), 0, c->stream, uN, uF,
+                           oN, oF, ox, oT, c->grid.V, ca.ref_cell, ca.n_ref, xfi, Tfi, xfo, Tfo, ca.nf,
+                           c->sorted_cell, c->sorted_idx, rate, ca.src_child, n_src, gc, cp, volf, c->cnt);
+    else
+        hipLaunchKernelGGL((k_crta_fine<G, S, false, false, NC, true>), dim3(fblk), dim3(tb), 0, c->stream, uN,
+                           uF, oN, oF, ox, oT, c->grid.V, ca.ref_cell, ca.n_ref, xfi, Tfi, xfo, Tfo, ca.nf,
+                           c->sorted_cell, c->sorted_idx, rate, ca.src_child, n_src, gc, cp, volf, c->cnt);
+    return check_launch(c, "k_crta_fine (tape)");
+}
+
 template <int G, typename S>
 static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double *x0, const double *T0,
                          const double *n0, const int64_t *cell, const double *rate, int n_src, double dt,
-                         int n_steps, S *gN, S *gF, double *gx, double *gT, double *g_n0, double *g_rate) {
+                         int n_steps, S *gN, S *gF, double *gx, double *gT, double *g_n0, double *g_rate,
+                         const CrtaAdj &ca = CrtaAdj{}) {
     const Grid gr = c->grid;
     const int64_t V = gr.V;
     const int tb = 256;
@@ -963,6 +1017,31 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     auto uN = [&](int s) { return keep_u ? (S *)c->adj.ustar + (int64_t)s * 4 * G * V : (S *)c->Ns; };
     auto uF = [&](int s) { return keep_u ? uN(s) + (int64_t)G * V : (S *)c->Fs; };
     if (int e = build_sources<G>(c, cell, rate, n_src)) return e;
+    // refined cells: their mask (the coarse chemistry and its adjoint skip
+    // them) and the children's tape, slot 0 the caller's
+    const bool crta = ca.n_ref > 0;
+    const uint32_t *skip = nullptr;
+    const int64_t nfine = (int64_t)ca.n_ref * ca.nc;
+    auto fx = [&](int s) { return s == 0 ? ca.xf0 : ca.tape + (int64_t)(s - 1) * 2 * nfine; };
+    auto fT = [&](int s) { return s == 0 ? ca.Tf0 : ca.tape + (int64_t)(s - 1) * 2 * nfine + nfine; };
+    if (crta) {
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((c->mask_words + tb - 1) / tb)), dim3(tb), 0, c->stream,
+                           c->refmask, c->mask_words, 0u);
+        hipLaunchKernelGGL(k_fill_u64, dim3((kCntSlots * CNT_COUNT + 255) / 256), dim3(256), 0, c->stream, c->cnt,
+                           (int)(kCntSlots * CNT_COUNT), 0ull);
+        hipLaunchKernelGGL(k_mark_refined, dim3((ca.n_ref + tb - 1) / tb), dim3(tb), 0, c->stream, ca.ref_cell,
+                           ca.n_ref, V, c->refmask, c->cnt);
+        if (int e = check_launch(c, "k_mark_refined")) return e;
+        // a repeated parent would have two sets of children writing its
+        // gradients: refuse the list instead (one small read-back)
+        std::vector<unsigned long long> slots((size_t)kCntSlots * CNT_COUNT);
+        HIP_TRY(c, hipMemcpyAsync(slots.data(), c->cnt, slots.size() * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        unsigned long long bad = 0;
+        for (int j = 0; j < kCntSlots; ++j) bad += slots[(size_t)j * CNT_COUNT + CNT_BADREF];
+        if (bad) return fail(c, EMMA_RT_EINVAL, "ref_cell has %llu entries outside the grid or repeated", bad);
+        skip = c->refmask;
+    }
     // the segment forward, step s into tape slot s + 1, marking the cells whose
     // subcycle was not a single substep
     const int64_t mwords = c->adj.multi_words;
@@ -970,10 +1049,21 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
     for (int s = 0; s < n_steps; ++s) {
         if (s + 1 < n_steps || keep_u)
             if (int e = tape_transport<G, S>(c, tN(s), tF(s), uN(s), uF(s), cp)) return e;
-        if (s + 1 < n_steps)
+        if (s + 1 < n_steps) {
             if (int e = tape_chem<G, S>(c, uN(s), uF(s), tx(s), tT(s), tN(s + 1), tF(s + 1), tx(s + 1), tT(s + 1),
-                                        n0, n_src, cp, multi(s)))
+                                        n0, n_src, cp, multi(s), skip))
                 return e;
+            if (crta) {
+                double *xo = (double *)fx(s + 1), *To = (double *)fT(s + 1);
+                const int e = ca.nc == 8
+                                  ? crta_tape_launch<G, S, 8>(c, uN(s), uF(s), tN(s + 1), tF(s + 1), tx(s + 1),
+                                                              tT(s + 1), fx(s), fT(s), xo, To, rate, n_src, gc, cp, ca)
+                                  : crta_tape_launch<G, S, 64>(c, uN(s), uF(s), tN(s + 1), tF(s + 1), tx(s + 1),
+                                                               tT(s + 1), fx(s), fT(s), xo, To, rate, n_src, gc, cp,
+                                                               ca);
+                if (e) return e;
+            }
+        }
     }
     SrcTable src{c->mask, c->sorted_cell, c->S, n_src};
     if (n_src > 0) {
@@ -1025,10 +1115,12 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
             const unsigned ablk = (unsigned)((V + atb - 1) / atb);
             if (fast)
                 hipLaunchKernelGGL((k_chem_adj<G, S, true>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms,
+                                   skip);
             else
                 hipLaunchKernelGGL((k_chem_adj<G, S, false>), dim3(ablk), dim3(atb), 0, c->stream, Ut, Ft, tx(s),
-                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms);
+                                   tT(s), n0, V, src, gc, cp, gN, gF, gx, gT, g_n0, c->adj.gS, (S *)c->adj.gU, wl, ms,
+                                   skip);
             if (int e = check_launch(c, "k_chem_adj")) return e;
         }
         if (side) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->adj.ev_out, 0));
@@ -1045,6 +1137,14 @@ static int adjoint_typed(emma_rt_ctx *c, const S *N0, const S *F0, const double 
                                    (S *)c->adj.gU, wl);
         }
         if (int e = check_launch(c, "k_chem_adj_list")) return e;
+        if (crta) {
+            Timed t(c, KID_ADJ_CHEM);
+            const int e = ca.nc == 8 ? crta_adj_launch<G, S, 8>(c, Ut, Ft, fx(s), fT(s), rate, n_src, gc, cp, ca, gN,
+                                                                gF, gx, gT, g_rate, (S *)c->adj.gU)
+                                     : crta_adj_launch<G, S, 64>(c, Ut, Ft, fx(s), fT(s), rate, n_src, gc, cp, ca,
+                                                                 gN, gF, gx, gT, g_rate, (S *)c->adj.gU);
+            if (e) return e;
+        }
         {
             Timed t(c, KID_ADJ_TRANSPORT);
             if (c->cfg.flux == EMMA_RT_FLUX_HLL) {
@@ -1109,6 +1209,66 @@ extern "C" int emma_rt_step_adjoint(emma_rt_ctx *c, const void *N0, const void *
         ADISPATCH(4)
     }
 #undef ADISPATCH
+    return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
+}
+
+extern "C" int64_t emma_rt_crta_adjoint_work_bytes(int32_t n_steps, int32_t n_ref, int32_t ratio) {
+    if (n_steps < 1 || n_ref < 0 || (ratio != 2 && ratio != 4)) return -1;
+    return (int64_t)(n_steps - 1) * n_ref * ratio * ratio * ratio * 16;
+}
+
+extern "C" int emma_rt_step_crta_adjoint(emma_rt_ctx *c, const void *N0, const void *F0, const double *x0,
+                                         const double *T0, const double *n0, const int64_t *cell,
+                                         const double *rate, const int32_t *src_child, int32_t n_src, double dt,
+                                         int32_t n_steps, const int64_t *ref_cell, int32_t n_ref, int32_t ratio,
+                                         const double *x_fine0, const double *T_fine0, const double *n_fine,
+                                         void *work, int64_t work_bytes, void *gN, void *gF, double *gx,
+                                         double *gT, double *g_n0, double *g_rate, double *g_x_fine,
+                                         double *g_T_fine, double *g_n_fine) {
+    if (!c) return fail(nullptr, EMMA_RT_EINVAL, "ctx is NULL");
+    if (c->cfg.adjoint_max_steps < 1) return fail(c, EMMA_RT_EINVAL, "context was created without adjoint scratch");
+    if (n_steps < 1 || n_steps > c->cfg.adjoint_max_steps)
+        return fail(c, EMMA_RT_EINVAL, "n_steps must be in 1..%d", c->cfg.adjoint_max_steps);
+    if (!N0 || !F0 || !x0 || !T0 || !n0 || !gN || !gF || !gx || !gT || !g_n0)
+        return fail(c, EMMA_RT_EINVAL, "a field pointer is NULL");
+    if (n_src < 0 || n_src > EMMA_RT_MAX_SOURCES)
+        return fail(c, EMMA_RT_EINVAL, "n_src must be in 0..%d", EMMA_RT_MAX_SOURCES);
+    if (n_src > 0 && (!cell || !rate || !g_rate)) return fail(c, EMMA_RT_EINVAL, "source arrays are NULL");
+    if (!(dt > 0) || dt > c->cfg.dx / (3.0 * c->cfg.c_red) * (1.0 + 1e-12))
+        return fail(c, EMMA_RT_EINVAL, "dt must be in (0, dx/(3 c_red)]");
+    if (ratio != 2 && ratio != 4) return fail(c, EMMA_RT_EINVAL, "ratio must be 2 or 4");
+    if (n_ref < 0 || (int64_t)n_ref > c->grid.V) return fail(c, EMMA_RT_EINVAL, "n_ref must be in 0..cells");
+    if ((int64_t)n_ref * ratio * ratio * ratio > ((int64_t)1 << 31) - 256)
+        return fail(c, EMMA_RT_EINVAL, "too many children (n_ref * ratio^3)");
+    if (n_ref > 0 && (!ref_cell || !x_fine0 || !T_fine0 || !n_fine || !g_x_fine || !g_T_fine || !g_n_fine))
+        return fail(c, EMMA_RT_EINVAL, "refined-cell arrays are NULL");
+    const int64_t need = emma_rt_crta_adjoint_work_bytes(n_steps, n_ref, ratio);
+    if (need > 0 && (!work || work_bytes < need))
+        return fail(c, EMMA_RT_EINVAL, "work must hold %lld bytes", (long long)need);
+    if (need > 0 && ((uintptr_t)work & 7)) return fail(c, EMMA_RT_EINVAL, "work must be 8-byte aligned");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != c->device) return fail(c, EMMA_RT_EINVAL, "current device %d is not the context's %d", dev, c->device);
+    c->err[0] = 0;
+    CrtaAdj ca{ref_cell, n_ref, ratio * ratio * ratio, src_child, x_fine0, T_fine0, n_fine, (double *)work,
+               g_x_fine, g_T_fine, g_n_fine};
+    const int G = c->cfg.n_groups;
+    const bool f64 = c->cfg.precision == EMMA_RT_FP64;
+#define RDISPATCH(GG)                                                                                        \
+    case GG:                                                                                                 \
+        return f64 ? adjoint_typed<GG, double>(c, (const double *)N0, (const double *)F0, x0, T0, n0, cell,  \
+                                               rate, n_src, dt, n_steps, (double *)gN, (double *)gF, gx, gT, \
+                                               g_n0, g_rate, ca)                                             \
+                   : adjoint_typed<GG, float>(c, (const float *)N0, (const float *)F0, x0, T0, n0, cell,     \
+                                              rate, n_src, dt, n_steps, (float *)gN, (float *)gF, gx, gT,    \
+                                              g_n0, g_rate, ca);
+    switch (G) {
+        RDISPATCH(1)
+        RDISPATCH(2)
+        RDISPATCH(3)
+        RDISPATCH(4)
+    }
+#undef RDISPATCH
     return fail(c, EMMA_RT_EINVAL, "n_groups out of range");
 }
 

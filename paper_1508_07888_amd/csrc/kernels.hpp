@@ -869,13 +869,17 @@ __device__ __forceinline__ double child_sum(double v) {
 // One lane per child: chemistry on the injected radiation, then the
 // restriction; lane 0 of each parent writes the parent.  Children's sources:
 // the parent's sources (sorted table, list order) whose child index is this
-// lane's, at rate * frac / volf, volf = (dx / r)^3.
-template <int G, typename S, bool DIAG, bool FAST, int NC>
+// lane's, at rate * frac / volf, volf = (dx / r)^3.  The children's state is
+// read from (xfi, Tfi) and written to (xf, Tf), which may be the same arrays.
+// TAPE (the adjoint's segment forward): Ns, Fs are the transport output before
+// the floor and the limiter, applied here to the parent's values with the
+// transport's own function.
+template <int G, typename S, bool DIAG, bool FAST, int NC, bool TAPE = false>
 __global__ __launch_bounds__(256) void k_crta_fine(const S *__restrict__ Ns, const S *__restrict__ Fs,
                                                    S *__restrict__ N, S *__restrict__ F, double *__restrict__ x,
                                                    double *__restrict__ T, int64_t V,
                                                    const int64_t *__restrict__ ref_cell, int n_ref,
-                                                   double *__restrict__ xf, double *__restrict__ Tf,
+                                                   const double *xfi, const double *Tfi, double *xf, double *Tf,
                                                    const double *__restrict__ nf,
                                                    const int64_t *__restrict__ sorted_cell,
                                                    const int32_t *__restrict__ sorted_idx,
@@ -894,9 +898,14 @@ __global__ __launch_bounds__(256) void k_crta_fine(const S *__restrict__ Ns, con
         double Nc[G], Fc[G][3], Sc[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            Nc[g] = (double)Ns[(int64_t)g * V + p];
+            S n = Ns[(int64_t)g * V + p];
+            S fv[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) Fc[g][k] = (double)Fs[((int64_t)g * 3 + k) * V + p];
+            for (int k = 0; k < 3; ++k) fv[k] = Fs[((int64_t)g * 3 + k) * V + p];
+            if (TAPE) floor_limit_fwd<S>(n, fv[0], fv[1], fv[2], (S)cp.c);
+            Nc[g] = (double)n;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Fc[g][k] = (double)fv[k];
             Sc[g] = 0.0;
         }
         if (n_src > 0) {
@@ -911,7 +920,7 @@ __global__ __launch_bounds__(256) void k_crta_fine(const S *__restrict__ Ns, con
             }
         }
         const int64_t f = j * NC + ch;
-        double xc = xf[f], Tc = Tf[f];
+        double xc = xfi[f], Tc = Tfi[f];
         const double nc = nf[f];
         st = chem_cell<G, FAST>(gc, cp, Nc, Fc, xc, Tc, nc, Sc);
         xf[f] = xc;

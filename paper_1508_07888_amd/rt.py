@@ -214,6 +214,44 @@ class EmmaRT:
         if rc != _lib.EMMA_RT_OK:
             raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))
 
+    def step_crta_adjoint(self, N0, F0, x0, T0, n0, src_cell, src_rate, dt, n_steps, ref_cell, ratio,
+                          x_fine0, T_fine0, n_fine, gN, gF, gx, gT, g_n0, g_rate, g_x_fine, g_T_fine,
+                          g_n_fine, src_child=None, work=None):
+        """The adjoint of step_crta, in place as step_adjoint; (g_x_fine,
+        g_T_fine) go from dL/d(children's end state) to dL/d(start state) and
+        g_n_fine is accumulated.  work: a device tensor of at least
+        crta_adjoint_work_bytes(n_steps, n_ref, ratio) bytes (allocated here
+        when None)."""
+        pN, pF, px, pT, pn = self._fields(N0, F0, x0, T0, n0)
+        qN, qF, qx, qT, qn = self._fields(gN, gF, gx, gT, g_n0)
+        n, pc, pr = self._sources(src_cell, src_rate)
+        qr = self._check(g_rate, "g_rate", torch.float64, (n,)) if n else 0
+        pch = self._check(src_child, "src_child", torch.int32, (n,)) if (n and src_child is not None) else 0
+        n_ref = int(ref_cell.numel())
+        nc = int(ratio) ** 3
+        if n_ref:
+            pref = self._check(ref_cell, "ref_cell", torch.int64, (n_ref,))
+            f = [self._check(t, name, torch.float64, (n_ref, nc)) for t, name in
+                 ((x_fine0, "x_fine0"), (T_fine0, "T_fine0"), (n_fine, "n_fine"), (g_x_fine, "g_x_fine"),
+                  (g_T_fine, "g_T_fine"), (g_n_fine, "g_n_fine"))]
+        else:
+            pref, f = 0, [0] * 6
+        need = _lib.emma_rt_crta_adjoint_work_bytes(n_steps, n_ref, ratio)
+        if need < 0:
+            raise ValueError("n_steps must be >= 1 and ratio 2 or 4")
+        if work is None and need > 0:
+            work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        pw, wb = 0, 0
+        if work is not None:
+            if work.device != self.device or not work.is_contiguous():
+                raise ValueError("work must be a contiguous tensor on the context's device")
+            pw, wb = work.data_ptr(), work.numel() * work.element_size()
+        rc = _lib.emma_rt_step_crta_adjoint(self._ctx, pN, pF, px, pT, pn, pc, pr, pch, n, dt, n_steps, pref,
+                                            n_ref, int(ratio), f[0], f[1], f[2], pw, wb, qN, qF, qx, qT, qn,
+                                            qr, f[3], f[4], f[5])
+        if rc != _lib.EMMA_RT_OK:
+            raise _lib.EmmaError(rc, _lib.emma_rt_last_error(self._ctx))
+
 
 class RTStep(torch.autograd.Function):
     """n_steps radiation steps as a differentiable map of (n0, src_rate, N, F, x, T).
