@@ -171,7 +171,7 @@ int emma_rt_step(emma_rt_ctx *ctx, void *N, void *F, double *x_HII, double *T,
  *                   the grid are ignored without a report)
  * Scratch needed, each piece rounded up to 256 bytes: 4 G V e (N and F; e = 4
  * mixed, 8 FP64) + 4 V (work list) + V/8 (source mask) + 24 n_src + 8 G n_src
- * (source table) + 14336 (counters) + 64 + (16 G + 40) C (continuation states
+ * (source table) + 14336 (counters) + 64 + (16 G + 44) C (continuation states
  * of the chemistry, C = min(V, max(65536, V/8)) slots).  A grid and source list needing more
  * than EMMA_RT_NOALLOC_SCRATCH_BYTES return EINVAL before anything runs (a
  * 128^3 grid with 3 groups in mixed precision fits; in FP64 it does not).

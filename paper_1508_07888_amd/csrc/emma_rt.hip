@@ -42,7 +42,8 @@ struct emma_rt_ctx {
     double *partial;             // [nblk][G+1]
     int diag_blocks;
     double *dsum;                // [G+1]
-    uint32_t *work_count;        // [1]: cells deferred by the first chemistry pass
+    uint32_t *work_count;        // [2]: cells deferred by the first chemistry pass; cells handed on
+                                 // to the cooperative pass
     uint32_t *work_cells;        // [V]
     int list_blocks;             // grid of the second chemistry pass
     void *cont;                  // continuation states of the stopped cells (ContBuf)
@@ -191,7 +192,7 @@ static uint32_t cont_capacity(int64_t V) {
     return (uint32_t)(cap < V ? cap : V);
 }
 
-static int64_t cont_bytes(int G, uint32_t cap) { return (int64_t)cap * ((2 * G + 3) * 8 + 16); }
+static int64_t cont_bytes(int G, uint32_t cap) { return (int64_t)cap * ((2 * G + 3) * 8 + 16 + 4); }
 
 static ContBuf cont_view(void *base, int G, uint32_t cap) {
     ContBuf cb;
@@ -202,6 +203,7 @@ static ContBuf cont_view(void *base, int G, uint32_t cap) {
     cb.e = cb.x + cap;
     cb.rem = cb.e + cap;
     cb.st = (int32_t *)(cb.rem + cap);
+    cb.next = (uint32_t *)(cb.st + (size_t)4 * cap);
     cb.cap = cap;
     return cb;
 }
@@ -396,25 +398,42 @@ static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, const doubl
     Timed t(c, KID_CHEM_LIST);
     const dim3 grid(nb), block(256);
     const int64_t V = c->grid.V;
-    if (Ns_pre) {
-        if (fast)
-            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F,
-                               T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb);
-        else
-            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F,
-                               T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb);
-    } else if (fast) {
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To,
-                           n0, V, src, gc, cp, c->cnt, wl, cb);
-    } else {
-        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
-                           To, n0, V, src, gc, cp, c->cnt, wl, cb);
+    // on-the-spot, energy-evolving mode: cells still going after
+    // kContBudget substeps finish in the cooperative pass (kCoopDirect: all
+    // stopped cells go there at once)
+    const bool coop = fast && kContBudget > 0;
+    const int budget = coop ? kContBudget : 0x7fffffff;
+    if (!(coop && kCoopDirect)) {
+        if (Ns_pre) {
+            if (fast)
+                hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true, true>), grid, block, 0, c->stream, Ns_pre, Fs, N,
+                                   F, T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+            else
+                hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false, true>), grid, block, 0, c->stream, Ns_pre, Fs, N,
+                                   F, T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+        } else if (fast) {
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
+                               To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+        } else {
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
+                               To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+        }
+        if (int e = check_launch(c, "k_chem_cont")) return e;
     }
-    return check_launch(c, "k_chem_cont");
+    if (!coop) return EMMA_RT_OK;
+    const int direct = kCoopDirect ? 1 : 0;
+    if (Ns_pre)
+        hipLaunchKernelGGL((k_chem_coop<G, S, DIAG, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F, T, xo, To,
+                           n0, V, src, gc, cp, c->cnt, wl, cb, direct);
+    else
+        hipLaunchKernelGGL((k_chem_coop<G, S, DIAG>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To, n0,
+                           V, src, gc, cp, c->cnt, wl, cb, direct);
+    return check_launch(c, "k_chem_coop");
 }
 
 static int reset_worklist(emma_rt_ctx *c) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->work_count, (int64_t)1, 0u);
+    // [0]: the first pass's stopped cells, [1]: the ones handed on to the cooperative pass
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, c->stream, c->work_count, (int64_t)2, 0u);
     return check_launch(c, "k_fill_u32 (work list)");
 }
 

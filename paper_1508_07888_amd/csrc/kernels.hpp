@@ -429,13 +429,24 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
 // whole wave for that long.  They are finished by a second, persistent pass
 // over the compacted list (same code, same inputs, same results).
 #ifndef EMMA_CHEM_BUDGET
-#define EMMA_CHEM_BUDGET 4
+#define EMMA_CHEM_BUDGET 3
 #endif
 #ifndef EMMA_CHEM_BUDGET_FUSED
 #define EMMA_CHEM_BUDGET_FUSED 2
 #endif
 constexpr int kChemBudget = EMMA_CHEM_BUDGET;
 constexpr int kChemBudgetFused = EMMA_CHEM_BUDGET_FUSED;
+// Total substeps after which the second pass hands a cell on to the
+// cooperative pass (0: no cooperative pass); with EMMA_COOP_DIRECT the
+// cooperative pass takes every stopped cell and the second pass is skipped.
+#ifndef EMMA_CONT_BUDGET
+#define EMMA_CONT_BUDGET 16
+#endif
+#ifndef EMMA_COOP_DIRECT
+#define EMMA_COOP_DIRECT 0
+#endif
+constexpr int kContBudget = EMMA_CONT_BUDGET;
+constexpr bool kCoopDirect = EMMA_COOP_DIRECT != 0;
 
 struct WorkList {
     uint32_t *count;  // [1], reset before every first pass
@@ -465,8 +476,23 @@ struct ContBuf {
     double *N, *Pf;       // [G][cap]
     double *x, *e, *rem;  // [cap]
     int32_t *st;          // [4][cap]: substeps, attempts, cap, xclamp
+    uint32_t *next;       // [cap]: slots the second pass hands on to the cooperative
+                          // pass (their count at WorkList::count[1])
     uint32_t cap;
 };
+
+// Appends v for every lane with push set to list (count at *count): one
+// atomic per wave.
+__device__ inline void list_push(uint32_t *count, uint32_t *list, bool push, uint32_t v) {
+    const unsigned long long m = __ballot(push);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == first) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = __shfl(base, first, 64);
+    if (push) list[base + __popcll(m & ((1ull << lane) - 1ull))] = v;
+}
 
 template <int G>
 __device__ __forceinline__ void cont_save(const ContBuf &cb, uint32_t k, const SubState<G> &s) {
@@ -622,11 +648,35 @@ __global__ __launch_bounds__(chem_tb<S>(), EMMA_CHEM_MIN_BLOCKS) void k_chem(
 // isothermal mode); writes N, F, xo, To of those cells.  TAPE: Ns, Fs are
 // the transport output before the floor and the limiter, as in k_chem (Ns is
 // read only then).
+// The end of a continued cell's subcycle: N, F = F* Pf, x, T of cell i.
+template <int G, typename S, bool FAST, bool TAPE>
+__device__ __forceinline__ void cont_store(const S *Ns, const S *Fs, S *N, S *F, double *xo, double *To, int64_t V,
+                                           int64_t i, const SubState<G> &s, const ChemParams &cp, double n0c,
+                                           double Tc) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        N[(int64_t)g * V + i] = (S)s.N[g];
+        S f[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[c] = Fs[((int64_t)g * 3 + c) * V + i];
+        if (TAPE) {
+            S n = Ns[(int64_t)g * V + i];
+            floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)cp.c);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F[((int64_t)g * 3 + c) * V + i] = (S)((double)f[c] * s.Pf[g]);
+    }
+    xo[i] = s.x;
+    To[i] = sub_T<G, FAST>(s, cp, n0c, Tc);
+}
+
+// budget: total accepted substeps after which a cell is handed on to the
+// cooperative pass (its state back in its slot, the slot appended to cb.next).
 template <int G, typename S, bool DIAG, bool FAST, bool TAPE = false>
 __global__ __launch_bounds__(256) void k_chem_cont(const S *Ns, const S *Fs, S *N, S *F, const double *T, double *xo, double *To,
                                                    const double *__restrict__ n0, int64_t V, SrcTable src,
                                                    GroupConsts gc, ChemParams cp, unsigned long long *cnt,
-                                                   WorkList wl, ContBuf cb) {
+                                                   WorkList wl, ContBuf cb, int budget) {
     const uint32_t n = min(*wl.count, cb.cap);
     const uint32_t stride = gridDim.x * blockDim.x;
     ChemStats tot{0, 0, 0, 0};
@@ -638,22 +688,11 @@ __global__ __launch_bounds__(256) void k_chem_cont(const S *Ns, const S *Fs, S *
         double Sc[G];
         source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
         const double n0c = n0[i], Tc = T[i];
-        sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, 0x7fffffff);
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            N[(int64_t)g * V + i] = (S)s.N[g];
-            S f[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) f[c] = Fs[((int64_t)g * 3 + c) * V + i];
-            if (TAPE) {
-                S n = Ns[(int64_t)g * V + i];
-                floor_limit_fwd<S>(n, f[0], f[1], f[2], (S)cp.c);
-            }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) F[((int64_t)g * 3 + c) * V + i] = (S)((double)f[c] * s.Pf[g]);
-        }
-        xo[i] = s.x;
-        To[i] = sub_T<G, FAST>(s, cp, n0c, Tc);
+        const bool handed = !sub_run<G, FAST>(s, gc, cp, n0c, Tc, Sc, budget);
+        if (handed) cont_save<G>(cb, k, s);
+        list_push(wl.count + 1, cb.next, handed, k);
+        if (handed) continue;  // counted by the cooperative pass
+        cont_store<G, S, FAST, TAPE>(Ns, Fs, N, F, xo, To, V, i, s, cp, n0c, Tc);
         if (DIAG) {
             tot.substeps += s.st.substeps;
             tot.attempts += s.st.attempts;
@@ -661,6 +700,157 @@ __global__ __launch_bounds__(256) void k_chem_cont(const S *Ns, const S *Fs, S *
             tot.xclamp += s.st.xclamp;
             maxsub = max(maxsub, s.st.substeps);
             atomicAdd(cnt_slot(cnt) + CNT_HIST + substep_bin(s.st.substeps), 1ull);
+        }
+    }
+    if (DIAG) {
+        wave_count(cnt, CNT_SUB, tot.substeps);
+        wave_count(cnt, CNT_ATT, tot.attempts);
+        wave_count(cnt, CNT_CAP, tot.cap);
+        wave_count(cnt, CNT_XCLAMP, tot.xclamp);
+        wave_count_max(cnt, CNT_MAXSUB, maxsub);
+    }
+}
+
+// ------------------------------------------------ cooperative long subcycles
+// The cells still short of dt after the second pass's budget (the heated
+// cells near the sources, up to ~100 substeps) are each one dependent chain:
+// a wave holding them runs for the longest one, alone on its SIMD, so the
+// chain's latency is the pass's time.  Here kCoopLanes lanes share a cell:
+// the rate fits of a substep are evaluated side by side (lane q of each quad
+// takes fit q, the four fits having one form, P exp(pre + a L - d ln(1 +
+// exp(c (L - ln b))))) and the attempts of the 10 % rule are tried side by
+// side (lane j with the first step halved j times, then 8 + j, ...), the
+// first accepted one kept.  Every lane runs the arithmetic of the per-cell
+// code on the same inputs, so the results (and the substep and attempt
+// counts) are the ones the per-cell subcycle would give.  On-the-spot,
+// energy-evolving mode only.
+constexpr int kCoopLanes = 8;
+
+// lane (q & 3) of a quad's value to every lane of the quad
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+    constexpr int ctrl = Q * 0x55;  // quad_perm [Q, Q, Q, Q]
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// rates_at<true>(T), each quad evaluating its four fits side by side
+__device__ __forceinline__ RateSet rates_coop(double T) {
+    const double invT = recip_fp64(T);
+    const double lam = 2.0 * kTHI * invT;
+    const double L = log_fp64(lam);
+    const double lnT = 12.662275226919286 - L;  // ln(2 T_HI) - L
+    const double sT = sqrt(T);
+    const int q = threadIdx.x & 3;
+    // 0: alpha_B, 1: recombination cooling, 2: collisional ionisation, 3:
+    // collisional excitation (a = d = c = 0: the fit part is exactly zero)
+    const double P = q == 0 ? 2.753e-14 : q == 1 ? 3.435e-30 * T : q == 2 ? 21.11 : 7.5e-19;
+    const double pre = q <= 1 ? -0.0 : q == 2 ? beta_pre(lnT, lam) : -118348.0 * invT;
+    const double a = q == 0 ? 1.500 : q == 1 ? 1.970 : q == 2 ? -1.089 : 0.0;
+    const double lnb = q == 0 ? 1.007957920399979 : q == 1 ? 0.8109302162163288 : q == 2 ? -1.0384583658483626 : 0.0;
+    const double c = q == 0 ? 0.407 : q == 1 ? 0.376 : q == 2 ? 0.874 : 0.0;
+    const double d = q == 0 ? 2.242 : q == 1 ? 3.720 : q == 2 ? 1.101 : 0.0;
+    const double R = recip_fp64(1.0 + sT * 0.003162277660168379);
+    const double v = P * exp_fp64(pre + hg_fit(L, a, lnb, c, d)) * (q == 3 ? R : 1.0);
+    RateSet r;
+    r.alpha = quad_bcast<0>(v);
+    r.dalpha = 0.0;
+    r.crec = quad_bcast<1>(v);
+    r.beta = quad_bcast<2>(v);
+    r.cci = kKB * kTHI * r.beta;
+    r.cce = quad_bcast<3>(v);
+    r.cff = 1.42e-27 * 1.3 * sT;
+    return r;
+}
+
+// substep<G, true> with the rates and the attempts shared by the lanes of a
+// group (every lane of the group holds the same cell state and ends with the
+// same new state)
+template <int G>
+__device__ __forceinline__ bool substep_coop(const GroupConsts &gc, const ChemParams &p, bool last, double n0,
+                                             double eunit, const double (&S)[G], double (&N)[G], double &x,
+                                             double &e, double &rem, double (&inv)[G], ChemStats &st) {
+    const double c = p.c;
+    if (!(e > 0.0 && e < HUGE_VAL)) return false;  // invalid input: leave the cell
+    const double Tp = e * recip_fp64(eunit * (1.0 + x));
+    const RateSet r = rates_coop(Tp);
+    double D;
+    int branch;
+    const double dtau0 = first_dtau<G>(gc, c, false, last, n0, r, N, x, e, rem, D, branch);
+    const int j = threadIdx.x & (kCoopLanes - 1);
+    const int base = (threadIdx.x & 63) & ~(kCoopLanes - 1);
+    double Nn[G], In[G], xn, en;
+    int xcl, k = 0, src = 0, flags = 0;
+    for (int round = 0;; ++round) {
+        // the attempt with the first step halved k times (exact: a power of 2)
+        k = kCoopLanes * round + j;
+        attempt<G>(gc, c, false, n0, r, S, N, x, e, ldexp(dtau0, -k), Nn, In, xn, en, xcl);
+        const bool pass = fabs(en - e) <= 0.1 * e;
+        const bool take = k <= kMaxHalvings && (last ? k == 0 : (pass || k == kMaxHalvings));
+        const unsigned m = (unsigned)(__ballot(take) >> base) & ((1u << kCoopLanes) - 1u);
+        if (m) {
+            src = base + __ffs(m) - 1;
+            flags = (xcl != 0) | ((!last && !pass) ? 2 : 0);  // clamp; cap reached without passing
+            break;
+        }
+    }
+    k = __shfl(k, src, 64);
+    flags = __shfl(flags, src, 64);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        N[g] = __shfl(Nn[g], src, 64);
+        inv[g] = __shfl(In[g], src, 64);
+    }
+    x = __shfl(xn, src, 64);
+    e = __shfl(en, src, 64);
+    st.attempts += k + 1;
+    if (flags & 2) st.cap = 1;
+    if (flags & 1) st.xclamp++;
+    rem = rem - ldexp(dtau0, -k);
+    st.substeps++;
+    return true;
+}
+
+// Third pass: the slots the second pass handed on (direct: every slot of the
+// work list), kCoopLanes lanes per cell, grid-stride.
+template <int G, typename S, bool DIAG, bool TAPE = false>
+__global__ __launch_bounds__(256) void k_chem_coop(const S *Ns, const S *Fs, S *N, S *F, const double *T,
+                                                   double *xo, double *To, const double *__restrict__ n0, int64_t V,
+                                                   SrcTable src, GroupConsts gc, ChemParams cp,
+                                                   unsigned long long *cnt, WorkList wl, ContBuf cb, int direct) {
+    const uint32_t n = direct ? min(*wl.count, cb.cap) : wl.count[1];
+    const uint32_t stride = gridDim.x * blockDim.x / kCoopLanes;
+    const bool lead = (threadIdx.x & (kCoopLanes - 1)) == 0;
+    ChemStats tot{0, 0, 0, 0};
+    int maxsub = 0;
+    for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kCoopLanes; q < n; q += stride) {
+        const uint32_t k = direct ? q : cb.next[q];
+        const int64_t i = wl.cells[k];
+        SubState<G> s;
+        cont_load<G>(cb, k, s);
+        double Sc[G];
+        source_of<G>(i, src.mask, src.sorted_cell, src.S, src.n, Sc);
+        const double n0c = n0[i], Tc = T[i];
+        const double eunit = 1.5 * n0c * kKB;
+        while (s.rem > 0.0) {
+            const bool last = s.st.substeps >= cp.max_substeps;
+            double inv[G];
+            if (!substep_coop<G>(gc, cp, last, n0c, eunit, Sc, s.N, s.x, s.e, s.rem, inv, s.st)) break;
+#pragma unroll
+            for (int g = 0; g < G; ++g) s.Pf[g] *= inv[g];
+            if (last) { s.st.cap = 1; break; }
+        }
+        if (lead) {
+            cont_store<G, S, true, TAPE>(Ns, Fs, N, F, xo, To, V, i, s, cp, n0c, Tc);
+            if (DIAG) {
+                tot.substeps += s.st.substeps;
+                tot.attempts += s.st.attempts;
+                tot.cap += s.st.cap;
+                tot.xclamp += s.st.xclamp;
+                maxsub = max(maxsub, s.st.substeps);
+                atomicAdd(cnt_slot(cnt) + CNT_HIST + substep_bin(s.st.substeps), 1ull);
+            }
         }
     }
     if (DIAG) {

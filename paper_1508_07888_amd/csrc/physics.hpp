@@ -168,9 +168,15 @@ struct RateSet {
 // L = ln(lam): A T^t exp(a L - d ln(1 + exp(c (L - ln b)))), i.e. two exp and
 // one log per fit instead of four pow (same value to a few ulp; ln(1 + u)
 // only needs a small ABSOLUTE error here since it is scaled by d inside exp).
+// The FMA is explicit so that every caller (the per-cell rates, the
+// cooperative rates of the long-subcycle pass, the adjoint) gets the same bits.
 __host__ __device__ __forceinline__ double hg_fit(double L, double a, double lnb, double c, double d) {
-    return a * L - d * log_fp64(1.0 + exp_fp64(c * (L - lnb)));
+    const double u = exp_fp64(c * (L - lnb));
+    return fma(a, L, -(d * log_fp64(1.0 + u)));
 }
+
+// exp(-lam/2) T^-1.5 part of the collisional-ionisation fit's exponent
+__host__ __device__ __forceinline__ double beta_pre(double lnT, double lam) { return fma(-0.5, lam, -1.5 * lnT); }
 
 template <bool OTSA>
 __host__ __device__ __forceinline__ RateSet rates_at(double T) {
@@ -191,7 +197,7 @@ __host__ __device__ __forceinline__ RateSet rates_at(double T) {
         r.crec = 1.778e-29 * T * exp_fp64(hg_fit(L, 1.965, -0.6143360001356555, 0.502, 2.697));  // ln 0.541
     }
     // 21.11 T^-1.5 exp(-lam/2) lam^-1.089 / (1 + (lam/0.354)^0.874)^1.101
-    r.beta = 21.11 * exp_fp64(-1.5 * lnT - 0.5 * lam + hg_fit(L, -1.089, -1.0384583658483626, 0.874, 1.101));  // ln 0.354
+    r.beta = 21.11 * exp_fp64(beta_pre(lnT, lam) + hg_fit(L, -1.089, -1.0384583658483626, 0.874, 1.101));  // ln 0.354
     r.cci = kKB * kTHI * r.beta;
     const double sT = sqrt(T);
     // 118348 K: collisional excitation temperature; sqrt(T / 1e5) = sT / 316.2...
@@ -219,7 +225,7 @@ __host__ __device__ inline void rates_and_dT(double T, RateSet &r, RateSet &d) {
     auto fit = [L](double a, double lnb, double c, double dd, double &slope) {
         const double u = exp_fp64(c * (L - lnb));
         slope = a - dd * c * u / (1.0 + u);
-        return a * L - dd * log_fp64(1.0 + u);
+        return fma(a, L, -(dd * log_fp64(1.0 + u)));
     };
     double sa, sc, sb;
     if (OTSA) {
@@ -242,7 +248,7 @@ __host__ __device__ inline void rates_and_dT(double T, RateSet &r, RateSet &d) {
         d.dalpha = daA - daB;
         d.crec = r.crec * (1.0 - sc) * invT;
     }
-    r.beta = 21.11 * exp_fp64(-1.5 * lnT - 0.5 * lam + fit(-1.089, -1.0384583658483626, 0.874, 1.101, sb));
+    r.beta = 21.11 * exp_fp64(beta_pre(lnT, lam) + fit(-1.089, -1.0384583658483626, 0.874, 1.101, sb));
     r.cci = kKB * kTHI * r.beta;
     const double sT = sqrt(T);
     r.cce = 7.5e-19 * exp_fp64(-118348.0 * invT) * recip_fp64(1.0 + sT * 0.003162277660168379);
@@ -287,6 +293,63 @@ struct SubInfo {
     int h;         // number of halvings of dtau0
     int xclamp;    // 0: none, -1: x' clamped to 0, +1: x' clamped to 1
 };
+
+// One attempt of a substep with step dtau from the start state (N, x, e):
+// N' (eq. e:therm1g), the factor inv[g] applied to F_g (eq. e:therm2g), x'
+// clamped to [0, 1] (eq. e:therm3; xcl the side it was clamped to) and e'
+// (eq. e:therm4; e itself in the isothermal mode).  This and first_dtau are
+// the steps of substep() below written out for the cooperative pass, in the
+// same operations; substep() keeps them inline (as calls they cost the
+// per-cell chemistry kernel 20 more registers and a wave per SIMD).
+template <int G>
+__host__ __device__ __forceinline__ void attempt(const GroupConsts &gc, double c, bool iso, double n0,
+                                                 const RateSet &r, const double (&S)[G], const double (&N)[G],
+                                                 double x, double e, double dtau, double (&Nn)[G],
+                                                 double (&inv)[G], double &xn, double &en, int &xcl) {
+    const double y0 = 1.0 - x;
+    double gam = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const double kap = c * gc.sigN[g] * y0 * n0;
+        const double rec = (g == 0) ? r.dalpha * x * x * n0 * n0 : 0.0;
+        inv[g] = recip_fp64(1.0 + dtau * kap);
+        Nn[g] = (N[g] + (S[g] + rec) * dtau) * inv[g];
+        gam += c * gc.sigN[g] * Nn[g];
+    }
+    xn = 1.0 - (r.alpha * x * x * n0 * dtau + y0) * recip_fp64(1.0 + dtau * (r.beta * x * n0 + gam));
+    xcl = 0;
+    if (xn < 0.0) { xn = 0.0; xcl = -1; }
+    if (xn > 1.0) { xn = 1.0; xcl = 1; }
+    if (iso) { en = e; return; }
+    double h = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) h += gc.SigE[g] * Nn[g];
+    en = e + dtau * c * (1.0 - xn) * n0 * h - dtau * cooling(r, n0, xn);
+}
+
+// The first attempt's step of a substep: dt_rem, or |e / (H - Lambda)| when
+// that is shorter (never on the guarded last substep).  D = H - Lambda.
+template <int G>
+__host__ __device__ __forceinline__ double first_dtau(const GroupConsts &gc, double c, bool iso, bool last,
+                                                      double n0, const RateSet &r, const double (&N)[G], double x,
+                                                      double e, double rem, double &D, int &branch) {
+    double dtau = rem;
+    D = 0.0;
+    branch = 0;
+    if (!iso && !last) {
+        double h = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) h += gc.SigE[g] * N[g];
+        const double H = c * (1.0 - x) * n0 * h;
+        const double L = cooling(r, n0, x);
+        D = H - L;
+        if (H != L) {
+            const double q = fabs(e * recip_fp64(D));
+            if (q < rem) { dtau = q; branch = 1; }
+        }
+    }
+    return dtau;
+}
 
 // One substep of the Sec. 2.2.4 sequence from the start state (N, x, e, rem):
 // dtau0 = min(rem, |e / (H - Lambda)|) (rem on the last, guarded substep),

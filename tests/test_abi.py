@@ -98,8 +98,8 @@ def test_scratch_bytes():
     b = _lib.emma_rt_scratch_bytes(c)
     V = 256 ** 3
     # N, F ping-pong; chemistry work list; continuation states (V/8 slots of
-    # 2G+3 doubles and 4 ints); source and refinement masks; then small tables
-    expected = 12 * V * 4 + 4 * V + (16 * 3 + 40) * (V // 8) + 2 * (V // 32) * 4
+    # 2G+3 doubles and 5 ints); source and refinement masks; then small tables
+    expected = 12 * V * 4 + 4 * V + (16 * 3 + 44) * (V // 8) + 2 * (V // 32) * 4
     assert expected <= b < expected + (8 << 20)
     assert _lib.emma_rt_scratch_bytes(_cfg(nx=0)) == -1
 
@@ -138,4 +138,4 @@ def test_noalloc_rejects_before_touching_the_gpu():
     # the largest 3-group mixed grid the header promises fits: 128^3 (argument
     # checks pass, so only the missing GPU stops the call here)
     V = 128 ** 3
-    assert 4 * 3 * V * 4 + 4 * V + V // 8 + 14336 + (16 * 3 + 40) * (V // 8) + 5 * 256 < _lib.NOALLOC_SCRATCH_BYTES
+    assert 4 * 3 * V * 4 + 4 * V + V // 8 + 14336 + (16 * 3 + 44) * (V // 8) + 5 * 256 < _lib.NOALLOC_SCRATCH_BYTES
