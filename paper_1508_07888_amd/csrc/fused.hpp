@@ -206,10 +206,9 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
     const R *__restrict__ Fin = a.F + (int64_t)3 * gy * V;
     R *__restrict__ Nout = a.No + (int64_t)gy * V;
     R *__restrict__ Fout = a.Fo + (int64_t)3 * gy * V;
-    Bounds<R> bd = a.bnd;
-    if (gy > 0)
-#pragma unroll
-        for (int f = 0; f < 6; ++f) bd.phi[f][0] = a.bnd.phi[f][gy];
+    // read in place from the arguments (a local copy indexed by face would
+    // live in scratch memory); the group's inflow fluxes are phi[face][gy + g]
+    const Bounds<R> &bd = a.bnd;
     // halo role as in k_tiled: 0 row below, 1 row above, 2 column left, 3 column right
     int hrole = -1, hlx = 0, hly = 0, hface = -1;
     uint32_t hcol = 0;
@@ -264,7 +263,7 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
         hkind = bd.kind[hface];
         hd = hface >> 1;
         hsgn = (hface & 1) ? R(-1) : R(1);
-        hphi = bd.phi[hface][0];
+        hphi = bd.phi[hface][gy];
     }
     const uint32_t hsrc = hrole >= 0 ? hcol : col;
     const R c = a.c;
@@ -279,8 +278,8 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
     Vec4<R> cur = load1(zwrap(z0) * plane + col);
     Vec4<R> nxt = load1(zwrap(min(z0 + 1, z1)) * plane + col);
     Vec4<R> um = load1(zwrap(z0 - 1) * plane + col);
-    if (z0 == 0 && zlo_ghost) um = ghost4(bd, 4, 0, c, cur);
-    if (z0 + 1 == nz && zhi_ghost) nxt = ghost4(bd, 5, 0, c, cur);
+    if (z0 == 0 && zlo_ghost) um = ghost4(bd, 4, gy, c, cur);
+    if (z0 + 1 == nz && zhi_ghost) nxt = ghost4(bd, 5, gy, c, cur);
     R Pc[6], Pn[6];
     Vec4<R> flo;
     {
@@ -366,7 +365,7 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
             st(Fout + 2 * V, zc * E, us.fz);
         }
         // roll the window
-        if (z + 2 == nz && zhi_ghost) nn = ghost4(bd, 5, 0, c, nxt);
+        if (z + 2 == nz && zhi_ghost) nn = ghost4(bd, 5, gy, c, nxt);
         m1_pressure(nn.n, nn.fx, nn.fy, nn.fz, c, Pnn);
         flo = fup;
         cur = nxt;
@@ -424,10 +423,9 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
     const R *__restrict__ Fin = a.F + (int64_t)3 * gy * V;
     R *__restrict__ Nout = a.No + (int64_t)gy * V;
     R *__restrict__ Fout = a.Fo + (int64_t)3 * gy * V;
-    Bounds<R> bd = a.bnd;
-    if (gy > 0)
-#pragma unroll
-        for (int f = 0; f < 6; ++f) bd.phi[f][0] = a.bnd.phi[f][gy];
+    // read in place from the arguments (a local copy indexed by face would
+    // live in scratch memory); the group's inflow fluxes are phi[face][gy + g]
+    const Bounds<R> &bd = a.bnd;
     int hrole = -1, hlx = 0, hly = 0, hface = -1;
     uint32_t hcol = 0;
     if (tid < kTX) {
@@ -503,7 +501,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
         hd = hface >> 1;
         hsgn = (hface & 1) ? R(-1) : R(1);
 #pragma unroll
-        for (int g = 0; g < G; ++g) hphi[g] = bd.phi[hface][g];
+        for (int g = 0; g < G; ++g) hphi[g] = bd.phi[hface][gy + g];
     }
     // threads without a halo cell reload their own column, except in the waves
     // that have no halo cell at all, which skip the halo loads (a wave-uniform
@@ -522,8 +520,8 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
             if (hwave) load_cell<G>(Nin, Fin, V, ((uint32_t)min(z0 + k, z1 - 1) * plane + hsrc) * E, H[k]);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (z0 == 0 && zlo_ghost) um[g] = ghost4(bd, 4, g, c, W[0][g]);
-            if (z0 + 1 == nz && zhi_ghost) W[1][g] = ghost4(bd, 5, g, c, W[0][g]);
+            if (z0 == 0 && zlo_ghost) um[g] = ghost4(bd, 4, gy + g, c, W[0][g]);
+            if (z0 + 1 == nz && zhi_ghost) W[1][g] = ghost4(bd, 5, gy + g, c, W[0][g]);
             R Pm[6];
             m1_pressure(um[g].n, um[g].fx, um[g].fy, um[g].fz, c, Pm, cc);
             Az2[g] = az2(um[g], Pm, c);
@@ -669,7 +667,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
         // plane z + 2 becomes the next step's upper neighbour
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            if (z + 2 == nz && zhi_ghost) nn[g] = ghost4(bd, 5, g, c, nxt[g]);  // nxt = plane nz-1
+            if (z + 2 == nz && zhi_ghost) nn[g] = ghost4(bd, 5, gy + g, c, nxt[g]);  // nxt = plane nz-1
             m1_pressure(nn[g].n, nn[g].fx, nn[g].fy, nn[g].fz, c, Pn[g], cc);
             Bz2[g] = bz2(nn[g], Pn[g], c);
         }
