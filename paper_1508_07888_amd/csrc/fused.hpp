@@ -49,7 +49,10 @@ constexpr int kTX = 64;
 #endif
 // prefetch depth of the z march (planes loaded ahead of use)
 #ifndef EMMA_PD_SPLIT
-#define EMMA_PD_SPLIT 4
+#define EMMA_PD_SPLIT 2
+#endif
+#ifndef EMMA_PD_SPLIT_FP64
+#define EMMA_PD_SPLIT_FP64 EMMA_PD_SPLIT
 #endif
 #ifndef EMMA_PD_FUSED
 #define EMMA_PD_FUSED 0
@@ -738,6 +741,7 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
                                   const Bounds<S> &bnd, bool nolimit = false) {
     // double tiles need twice the LDS: at most 8 rows (136 KB)
     constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
+    constexpr int PD = sizeof(S) == 8 ? EMMA_PD_SPLIT_FP64 : EMMA_PD_SPLIT;
     const int LZ = pick_lz(gr, TY);
     if (EMMA_SPLIT_ONE_LAUNCH) {
         // all groups in one launch (blockIdx.y = group): no tail and launch gap between groups
@@ -746,10 +750,10 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
         a.nolimit = nolimit ? 1 : 0;
         const int nb = a.ntx * a.nty * a.ntz;
         if (gr.nx % kTX == 0 && gr.ny % TY == 0)
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, true>), dim3(nb, G),
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb, G),
                                dim3(kTX * TY), 0, st, a);
         else
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, false>), dim3(nb, G),
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb, G),
                                dim3(kTX * TY), 0, st, a);
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
@@ -762,10 +766,10 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
         a.nolimit = nolimit ? 1 : 0;
         const int nb = a.ntx * a.nty * a.ntz;
         if (gr.nx % kTX == 0 && gr.ny % TY == 0)
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, true>), dim3(nb),
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb),
                                dim3(kTX * TY), 0, st, a);
         else
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, EMMA_PD_SPLIT, false>), dim3(nb),
+            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb),
                                dim3(kTX * TY), 0, st, a);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
