@@ -122,8 +122,12 @@ def _kind(name, precision="mixed"):
         return "adj_chemistry", targs[1] == storage
     if "k_transport_adj<" in name:
         return "adj_transport", targs[0] == storage
-    if "k_tiled" in name:
+    if "k_tiled_hll<" in name:  # <storage, DIAG, TY, FULL>
+        return "transport", targs[0] == storage and targs[1] == "false"
+    if "k_tiled<" in name:
         return ("fused_step" if targs[3] == "true" else "transport"), product
+    if "k_step_cell<" in name:
+        return "fused_step", product
     if "k_step_ws<" in name:
         return "fused_step", product
     if "k_chem<" in name:
