@@ -24,6 +24,12 @@ def test_kernel_kinds_select_the_product_instantiation_of_the_precision():
     assert bench._kind(tiled) == ("transport", True)
     fused = "void emma::k_tiled<3, float, false, true, true, 4, 0, true>(emma::TileArgs<float>)"
     assert bench._kind(fused) == ("fused_step", True)
+    # the HLL tiled transport: <storage, DIAG, tile rows, whole tiles>
+    hll = "void emma::k_tiled_hll<float, false, 4, true>(emma::TileArgs<float>)"
+    assert bench._kind(hll) == ("transport", True)
+    assert bench._kind(hll.replace("float, false", "float, true")) == ("transport", False)
+    assert bench._kind(hll.replace("float", "double"), "fp64") == ("transport", True)
+    assert bench._kind("void emma::k_step_cell<3, float, false, true>(float const*)") == ("fused_step", True)
     assert bench._kind("void at::native::vectorized_elementwise_kernel<4, ...>") == (None, False)
 
 
