@@ -399,35 +399,31 @@ static int launch_chem_cont(emma_rt_ctx *c, const S *Fs, S *N, S *F, const doubl
     const dim3 grid(nb), block(256);
     const int64_t V = c->grid.V;
     // on-the-spot, energy-evolving mode: cells still going after
-    // kContBudget substeps finish in the cooperative pass (kCoopDirect: all
-    // stopped cells go there at once)
+    // kContBudget substeps finish in the cooperative pass
     const bool coop = fast && kContBudget > 0;
     const int budget = coop ? kContBudget : 0x7fffffff;
-    if (!(coop && kCoopDirect)) {
-        if (Ns_pre) {
-            if (fast)
-                hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true, true>), grid, block, 0, c->stream, Ns_pre, Fs, N,
-                                   F, T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
-            else
-                hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false, true>), grid, block, 0, c->stream, Ns_pre, Fs, N,
-                                   F, T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
-        } else if (fast) {
-            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
-                               To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
-        } else {
-            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo,
-                               To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
-        }
-        if (int e = check_launch(c, "k_chem_cont")) return e;
+    if (Ns_pre) {
+        if (fast)
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F, T,
+                               xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+        else
+            hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F,
+                               T, xo, To, n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+    } else if (fast) {
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, true>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To,
+                           n0, V, src, gc, cp, c->cnt, wl, cb, budget);
+    } else {
+        hipLaunchKernelGGL((k_chem_cont<G, S, DIAG, false>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To,
+                           n0, V, src, gc, cp, c->cnt, wl, cb, budget);
     }
+    if (int e = check_launch(c, "k_chem_cont")) return e;
     if (!coop) return EMMA_RT_OK;
-    const int direct = kCoopDirect ? 1 : 0;
     if (Ns_pre)
         hipLaunchKernelGGL((k_chem_coop<G, S, DIAG, true>), grid, block, 0, c->stream, Ns_pre, Fs, N, F, T, xo, To,
-                           n0, V, src, gc, cp, c->cnt, wl, cb, direct);
+                           n0, V, src, gc, cp, c->cnt, wl, cb);
     else
         hipLaunchKernelGGL((k_chem_coop<G, S, DIAG>), grid, block, 0, c->stream, nullptr, Fs, N, F, T, xo, To, n0,
-                           V, src, gc, cp, c->cnt, wl, cb, direct);
+                           V, src, gc, cp, c->cnt, wl, cb);
     return check_launch(c, "k_chem_coop");
 }
 

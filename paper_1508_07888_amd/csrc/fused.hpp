@@ -39,14 +39,6 @@ constexpr int kTX = 64;
 #ifndef EMMA_LZ_MAX
 #define EMMA_LZ_MAX 32
 #endif
-// waves of a k_tiled block without any halo cell skip the halo loads (1)
-#ifndef EMMA_HALO_SKIP
-#define EMMA_HALO_SKIP 1
-#endif
-// split transport: all groups in one launch (1) or one launch per group (0)
-#ifndef EMMA_SPLIT_ONE_LAUNCH
-#define EMMA_SPLIT_ONE_LAUNCH 1
-#endif
 // prefetch depth of the z march (planes loaded ahead of use)
 #ifndef EMMA_PD_SPLIT
 #define EMMA_PD_SPLIT 2
@@ -510,7 +502,7 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
     // that have no halo cell at all, which skip the halo loads (a wave-uniform
     // condition, so a scalar branch)
     const uint32_t hsrc = hrole >= 0 ? hcol : col;
-    const bool hwave = !EMMA_HALO_SKIP || __builtin_amdgcn_readfirstlane(tid >> 6) * kTX < 2 * kTX + 2 * TY;
+    const bool hwave = __builtin_amdgcn_readfirstlane(tid >> 6) * kTX < 2 * kTX + 2 * TY;
 
     auto zwrap = [nz](int z) { return (uint32_t)((z % nz + nz) % nz); };
     {
@@ -733,8 +725,8 @@ inline bool tiled_supported(const Grid &gr) { return (uint64_t)gr.V * 8 < ((uint
 
 // Transport only (split path): the kernel for one group (one group's
 // rolling window in registers instead of all G), launched once for all
-// groups with the group in blockIdx.y (0.436 -> 0.411 ms per 256^3 step
-// against one launch per group: no tail and launch gap between groups).
+// groups with the group in blockIdx.y (no tail and launch gap between
+// groups, as one launch per group had).
 template <int G, typename S, bool DIAG>
 inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
                                   const ChemParams &cp, double lam, unsigned long long *cnt,
@@ -743,39 +735,18 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
     constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
     constexpr int PD = sizeof(S) == 8 ? EMMA_PD_SPLIT_FP64 : EMMA_PD_SPLIT;
     const int LZ = pick_lz(gr, TY);
-    if (EMMA_SPLIT_ONE_LAUNCH) {
-        // all groups in one launch (blockIdx.y = group): no tail and launch gap between groups
-        TileArgs<S> a = tile_args<1, S>(iN, iF, oN, oF, nullptr, nullptr, nullptr, gr, SrcTable{}, GroupConsts{},
-                                        cp, lam, cnt, LZ, WorkList{}, TY, bnd);
-        a.nolimit = nolimit ? 1 : 0;
-        const int nb = a.ntx * a.nty * a.ntz;
-        if (gr.nx % kTX == 0 && gr.ny % TY == 0)
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb, G),
-                               dim3(kTX * TY), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb, G),
-                               dim3(kTX * TY), 0, st, a);
-        return hipGetLastError() == hipSuccess ? 0 : -1;
-    }
-    for (int g = 0; g < G; ++g) {
-        Bounds<S> bg = bnd;  // this launch's group is group 0 of the kernel
-        for (int f = 0; f < 6; ++f) bg.phi[f][0] = bnd.phi[f][g];
-        TileArgs<S> a = tile_args<1, S>(iN + (int64_t)g * gr.V, iF + (int64_t)3 * g * gr.V, oN + (int64_t)g * gr.V,
-                                        oF + (int64_t)3 * g * gr.V, nullptr, nullptr, nullptr, gr, SrcTable{},
-                                        GroupConsts{}, cp, lam, cnt, LZ, WorkList{}, TY, bg);
-        a.nolimit = nolimit ? 1 : 0;
-        const int nb = a.ntx * a.nty * a.ntz;
-        if (gr.nx % kTX == 0 && gr.ny % TY == 0)
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb),
-                               dim3(kTX * TY), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb),
-                               dim3(kTX * TY), 0, st, a);
-    }
+    TileArgs<S> a = tile_args<1, S>(iN, iF, oN, oF, nullptr, nullptr, nullptr, gr, SrcTable{}, GroupConsts{}, cp,
+                                    lam, cnt, LZ, WorkList{}, TY, bnd);
+    a.nolimit = nolimit ? 1 : 0;
+    const int nb = a.ntx * a.nty * a.ntz;
+    if (gr.nx % kTX == 0 && gr.ny % TY == 0)
+        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Split-path transport with the HLL flux: one launch per group.
+// Split-path transport with the HLL flux: one launch for all groups.
 template <int G, typename S, bool DIAG>
 inline int launch_transport_tiled_hll(hipStream_t st, const S *iN, const S *iF, S *oN, S *oF, const Grid &gr,
                                       const ChemParams &cp, double lam, unsigned long long *cnt,

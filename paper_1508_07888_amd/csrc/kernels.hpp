@@ -437,16 +437,11 @@ __global__ __launch_bounds__(256) void k_transport(const R *__restrict__ N, cons
 constexpr int kChemBudget = EMMA_CHEM_BUDGET;
 constexpr int kChemBudgetFused = EMMA_CHEM_BUDGET_FUSED;
 // Total substeps after which the second pass hands a cell on to the
-// cooperative pass (0: no cooperative pass); with EMMA_COOP_DIRECT the
-// cooperative pass takes every stopped cell and the second pass is skipped.
+// cooperative pass (0: no cooperative pass).
 #ifndef EMMA_CONT_BUDGET
 #define EMMA_CONT_BUDGET 16
 #endif
-#ifndef EMMA_COOP_DIRECT
-#define EMMA_COOP_DIRECT 0
-#endif
 constexpr int kContBudget = EMMA_CONT_BUDGET;
-constexpr bool kCoopDirect = EMMA_COOP_DIRECT != 0;
 
 struct WorkList {
     uint32_t *count;  // [1], reset before every first pass
@@ -782,6 +777,8 @@ __device__ __forceinline__ bool substep_coop(const GroupConsts &gc, const ChemPa
     const int base = (threadIdx.x & 63) & ~(kCoopLanes - 1);
     double Nn[G], In[G], xn, en;
     int xcl, k = 0, src = 0, flags = 0;
+    // ends by round kMaxHalvings / kCoopLanes at the latest: the attempt with
+    // kMaxHalvings halvings is taken whether or not it passes (as substep())
     for (int round = 0;; ++round) {
         // the attempt with the first step halved k times (exact: a power of 2)
         k = kCoopLanes * round + j;
@@ -812,20 +809,20 @@ __device__ __forceinline__ bool substep_coop(const GroupConsts &gc, const ChemPa
     return true;
 }
 
-// Third pass: the slots the second pass handed on (direct: every slot of the
-// work list), kCoopLanes lanes per cell, grid-stride.
+// Third pass: the slots the second pass handed on, kCoopLanes lanes per
+// cell, grid-stride.
 template <int G, typename S, bool DIAG, bool TAPE = false>
 __global__ __launch_bounds__(256) void k_chem_coop(const S *Ns, const S *Fs, S *N, S *F, const double *T,
                                                    double *xo, double *To, const double *__restrict__ n0, int64_t V,
                                                    SrcTable src, GroupConsts gc, ChemParams cp,
-                                                   unsigned long long *cnt, WorkList wl, ContBuf cb, int direct) {
-    const uint32_t n = direct ? min(*wl.count, cb.cap) : wl.count[1];
+                                                   unsigned long long *cnt, WorkList wl, ContBuf cb) {
+    const uint32_t n = wl.count[1];
     const uint32_t stride = gridDim.x * blockDim.x / kCoopLanes;
     const bool lead = (threadIdx.x & (kCoopLanes - 1)) == 0;
     ChemStats tot{0, 0, 0, 0};
     int maxsub = 0;
     for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kCoopLanes; q < n; q += stride) {
-        const uint32_t k = direct ? q : cb.next[q];
+        const uint32_t k = cb.next[q];
         const int64_t i = wl.cells[k];
         SubState<G> s;
         cont_load<G>(cb, k, s);
