@@ -43,8 +43,14 @@ constexpr int kTX = 64;
 #ifndef EMMA_PD_SPLIT
 #define EMMA_PD_SPLIT 2
 #endif
+// FP64: one plane ahead and one LDS buffer (35 KB a block, 164 VGPRs: three
+// waves per SIMD, where two buffers held it to two blocks per CU)
 #ifndef EMMA_PD_SPLIT_FP64
-#define EMMA_PD_SPLIT_FP64 EMMA_PD_SPLIT
+#define EMMA_PD_SPLIT_FP64 1
+#endif
+// LDS buffers of the FP64 split transport's plane exchange (2 or 1)
+#ifndef EMMA_NB_SPLIT_FP64
+#define EMMA_NB_SPLIT_FP64 1
 #endif
 #ifndef EMMA_PD_FUSED
 #define EMMA_PD_FUSED 0
@@ -384,16 +390,17 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
 #ifndef EMMA_FUSED_MIN_BLOCKS
 #define EMMA_FUSED_MIN_BLOCKS 2
 #endif
-template <int G, typename R, bool DIAG, bool FUSE, bool FAST, int TY, int PD, bool FULL>
+template <int G, typename R, bool DIAG, bool FUSE, bool FAST, int TY, int PD, bool FULL, int NB = 2>
 __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN_BLOCKS : 1) void k_tiled(TileArgs<R> a) {
-    // plane z of the current group, double-buffered: only the split vectors a
-    // neighbour reads.  Consumer (ty, tx) reads lAx[ty][tx] (left cell's A_x),
-    // lBx[ty][tx + 1] (right cell's B_x), lAy[ty][tx] (A_y of the cell below),
-    // lBy[ty][tx] (B_y of the cell above).
-    __shared__ Vec4<R> lAx[2][TY][kTX + 1];
-    __shared__ Vec4<R> lBx[2][TY][kTX + 1];
-    __shared__ Vec4<R> lAy[2][TY + 1][kTX];
-    __shared__ Vec4<R> lBy[2][TY][kTX];
+    // plane z of the current group, double-buffered (NB = 2; NB = 1: one
+    // buffer and a second barrier per plane, half the LDS): only the split
+    // vectors a neighbour reads.  Consumer (ty, tx) reads lAx[ty][tx] (left
+    // cell's A_x), lBx[ty][tx + 1] (right cell's B_x), lAy[ty][tx] (A_y of the
+    // cell below), lBy[ty][tx] (B_y of the cell above).
+    __shared__ Vec4<R> lAx[NB][TY][kTX + 1];
+    __shared__ Vec4<R> lBx[NB][TY][kTX + 1];
+    __shared__ Vec4<R> lAy[NB][TY + 1][kTX];
+    __shared__ Vec4<R> lBy[NB][TY][kTX];
     const int tid = threadIdx.x;
     const int tx = tid & (kTX - 1), ty = tid >> 6;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -596,7 +603,8 @@ __global__ __launch_bounds__(kTX * TY, (FUSE && sizeof(R) == 4) ? EMMA_FUSED_MIN
                 }
                 us[g] = Vec4<R>{n, fx, fy, fz};
             }
-            buf ^= 1;
+            if (NB == 2) buf ^= 1;
+            else __syncthreads();  // every read of this plane before the next writes
         }
 
         // roll the z window before the chemistry so that plane z's state and
@@ -734,15 +742,16 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
     // double tiles need twice the LDS: at most 8 rows (136 KB)
     constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
     constexpr int PD = sizeof(S) == 8 ? EMMA_PD_SPLIT_FP64 : EMMA_PD_SPLIT;
+    constexpr int NB = sizeof(S) == 8 ? EMMA_NB_SPLIT_FP64 : 2;
     const int LZ = pick_lz(gr, TY);
     TileArgs<S> a = tile_args<1, S>(iN, iF, oN, oF, nullptr, nullptr, nullptr, gr, SrcTable{}, GroupConsts{}, cp,
                                     lam, cnt, LZ, WorkList{}, TY, bnd);
     a.nolimit = nolimit ? 1 : 0;
     const int nb = a.ntx * a.nty * a.ntz;
     if (gr.nx % kTX == 0 && gr.ny % TY == 0)
-        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
+        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, true, NB>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
     else
-        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
+        hipLaunchKernelGGL((k_tiled<1, S, DIAG, false, false, TY, PD, false, NB>), dim3(nb, G), dim3(kTX * TY), 0, st, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
