@@ -7,7 +7,9 @@ the GPU.
    ragged grids with sources in refined and plain cells, both ratios, both
    fluxes, on-the-spot and case A, several steps, through the C ABI.
 2. With no refined cells the call is emma_rt_step_adjoint, bit for bit.
-3. Argument errors, repeated or out-of-grid parents included.
+3. The mixed path's gradients against the FP64 path's, within 1e-3
+   normwise (about 1e-7 measured).
+4. Argument errors, repeated or out-of-grid parents included.
 """
 import numpy as np
 import pytest
@@ -124,6 +126,44 @@ def test_crta_adjoint_without_refined_cells_is_the_plain_adjoint(precision):
     for a, b in zip(*res):
         assert np.array_equal(a, b)
     rt.close()
+
+
+@pytest.mark.parametrize("ratio", [2, 4])
+def test_mixed_crta_adjoint_close_to_fp64(ratio):
+    """The mixed path's refined-cell adjoint (FP32 N, F and their gradients,
+    FP64 chemistry) against the FP64 one on the same inputs: dL/dn_H, the
+    rates, n_fine and the children's x_HII, T, where the loss weights the
+    end state (x_HII of coarse and fine cells, T) within 1e-3 normwise."""
+    k = _case((6, 7, 9), 2, ratio, 40 + ratio, 10)
+    steps = 3
+    rng = np.random.default_rng(ratio)
+    wx = rng.standard_normal(k["x"].shape)
+    wT = rng.standard_normal(k["T"].shape) / np.abs(k["T"]).max()
+    wxf = rng.standard_normal(k["xf"].shape)
+    wTf = rng.standard_normal(k["Tf"].shape) / np.abs(k["Tf"]).max()
+    res = {}
+    for precision in ("fp64", "mixed"):
+        rt = _rt(k, steps, precision=precision)
+        fdt = rt.dtype
+        gN = torch.zeros(k["N"].shape, dtype=fdt, device=DEV)
+        gF = torch.zeros(k["F"].shape, dtype=fdt, device=DEV)
+        gx, gT, gxf, gTf = to_dev(wx), to_dev(wT), to_dev(wxf), to_dev(wTf)
+        g_n0 = torch.zeros(k["shape"], dtype=torch.float64, device=DEV)
+        g_rate = torch.zeros(k["rates"].size, dtype=torch.float64, device=DEV)
+        g_nf = torch.zeros(k["nf"].shape, dtype=torch.float64, device=DEV)
+        rt.step_crta_adjoint(to_dev(k["N"], fdt), to_dev(k["F"], fdt), to_dev(k["x"]), to_dev(k["T"]),
+                             to_dev(k["n0"]), to_dev(k["cells"], torch.int64), to_dev(k["rates"]), k["dt"], steps,
+                             to_dev(k["ref"], torch.int64), ratio, to_dev(k["xf"]), to_dev(k["Tf"]), to_dev(k["nf"]),
+                             gN, gF, gx, gT, g_n0, g_rate, gxf, gTf, g_nf,
+                             src_child=to_dev(k["child"], torch.int32))
+        torch.cuda.synchronize()
+        res[precision] = [t.double().cpu().numpy() for t in (g_n0, g_rate, g_nf, gxf, gTf, gx, gT)]
+        rt.close()
+    names = ("n_H", "rate", "n_fine", "x_fine", "T_fine", "x", "T")
+    for name, a, b in zip(names, res["mixed"], res["fp64"]):
+        err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+        print(f"r={ratio} {name}: mixed vs fp64 gradient normwise {err:.2e}", flush=True)
+        assert err <= 1e-3, name
 
 
 def test_crta_adjoint_argument_errors():
