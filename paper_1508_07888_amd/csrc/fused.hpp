@@ -176,18 +176,24 @@ __device__ __forceinline__ Vec4<R> hll_face(const Vec4<R> &uL, const Vec4<R> &fL
                    (ap * fL.fz - am * fR.fz + pm * (uR.fz - uL.fz)) * inv};
 }
 
-// Split-path transport with the HLL flux, one group per launch (group 0 of
-// the arguments), blocks of 64 x TY columns marching up LZ-plane z chunks.
-// Halo roles, ghosts and the z window follow k_tiled; LDS holds, per plane
-// (double-buffered), U of the tile and its x/y halo, Ft_x and the x speeds of
-// the tile and its x halo, Ft_y and the y speeds of the tile and its y halo.
-template <typename R, bool DIAG, int TY, bool FULL>
+// Split-path transport with the HLL flux, the group in blockIdx.y, blocks of
+// 64 x TY columns marching up LZ-plane z chunks.  Halo roles, ghosts and the
+// z window follow k_tiled; LDS holds, per plane (NB = 2: double-buffered;
+// NB = 1: one buffer and a second barrier per plane), U of the tile and its
+// x/y halo, Ft_x and the x speeds of the tile and its x halo, Ft_y and the y
+// speeds of the tile and its y halo.  One buffer (22 KB FP32, 44 KB FP64)
+// measured faster than two: the FP64 double-buffered tiles (88 KB) fit once
+// per CU (FP64 HLL step 2.69 -> 1.92 ms at 256^3; FP32 1.009 -> 1.002).
+#ifndef EMMA_HLL_NB
+#define EMMA_HLL_NB 1
+#endif
+template <typename R, bool DIAG, int TY, bool FULL, int NB = EMMA_HLL_NB>
 __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
-    __shared__ Vec4<R> lU[2][TY + 2][kTX + 2];
-    __shared__ Vec4<R> lFx[2][TY][kTX + 2];
-    __shared__ Speeds2<R> lSx[2][TY][kTX + 2];
-    __shared__ Vec4<R> lFy[2][TY + 2][kTX];
-    __shared__ Speeds2<R> lSy[2][TY + 2][kTX];
+    __shared__ Vec4<R> lU[NB][TY + 2][kTX + 2];
+    __shared__ Vec4<R> lFx[NB][TY][kTX + 2];
+    __shared__ Speeds2<R> lSx[NB][TY][kTX + 2];
+    __shared__ Vec4<R> lFy[NB][TY + 2][kTX];
+    __shared__ Speeds2<R> lSy[NB][TY + 2][kTX];
     const int tid = threadIdx.x;
     const int tx = tid & (kTX - 1), ty = tid >> 6;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -377,7 +383,8 @@ __global__ __launch_bounds__(kTX * TY) void k_tiled_hll(TileArgs<R> a) {
             Pn[q] = Pnn[q];
         }
         hal = hal_next;
-        buf ^= 1;
+        if (NB == 2) buf ^= 1;
+        else __syncthreads();  // every read of this plane before the next writes
     }
     if (DIAG) {
         wave_count(a.cnt, CNT_LIMITER, nlim);
