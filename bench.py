@@ -643,7 +643,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5,
                     help="further timed calls of the same steps from fresh copies (median, min, max)")
     ap.add_argument("--path", default="split", choices=["split", "fused", "reference"],
-                    help="kernel path (all compute the same step; fused is the product path)")
+                    help="kernel path (all compute the same step; split is the default and the fastest)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling rocprofv3 byte counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
