@@ -39,9 +39,11 @@ constexpr int kTX = 64;
 #ifndef EMMA_LZ_MAX
 #define EMMA_LZ_MAX 32
 #endif
-// prefetch depth of the z march (planes loaded ahead of use)
+// prefetch depth of the z march (planes loaded ahead of use); FP32: one
+// plane ahead and one LDS buffer (17.5 KB a block, 90 VGPRs: five waves per
+// SIMD, where two buffers held it to four blocks per CU by their LDS)
 #ifndef EMMA_PD_SPLIT
-#define EMMA_PD_SPLIT 2
+#define EMMA_PD_SPLIT 1
 #endif
 // FP64: one plane ahead and one LDS buffer (35 KB a block, 164 VGPRs: three
 // waves per SIMD, where two buffers held it to two blocks per CU)
@@ -51,6 +53,10 @@ constexpr int kTX = 64;
 // LDS buffers of the FP64 split transport's plane exchange (2 or 1)
 #ifndef EMMA_NB_SPLIT_FP64
 #define EMMA_NB_SPLIT_FP64 1
+#endif
+// LDS buffers of the FP32 split transport's plane exchange (2 or 1)
+#ifndef EMMA_NB_SPLIT
+#define EMMA_NB_SPLIT 1
 #endif
 #ifndef EMMA_PD_FUSED
 #define EMMA_PD_FUSED 0
@@ -749,7 +755,7 @@ inline int launch_transport_tiled(hipStream_t st, const S *iN, const S *iF, S *o
     // double tiles need twice the LDS: at most 8 rows (136 KB)
     constexpr int TY = (sizeof(S) == 8 && EMMA_TY_SPLIT > 8) ? 8 : EMMA_TY_SPLIT;
     constexpr int PD = sizeof(S) == 8 ? EMMA_PD_SPLIT_FP64 : EMMA_PD_SPLIT;
-    constexpr int NB = sizeof(S) == 8 ? EMMA_NB_SPLIT_FP64 : 2;
+    constexpr int NB = sizeof(S) == 8 ? EMMA_NB_SPLIT_FP64 : EMMA_NB_SPLIT;
     const int LZ = pick_lz(gr, TY);
     TileArgs<S> a = tile_args<1, S>(iN, iF, oN, oF, nullptr, nullptr, nullptr, gr, SrcTable{}, GroupConsts{}, cp,
                                     lam, cnt, LZ, WorkList{}, TY, bnd);
