@@ -22,6 +22,11 @@ def test_kernel_kinds_select_the_product_instantiation_of_the_precision():
     assert bench._kind(chem.replace("float", "double"), "fp64") == ("chemistry", True)
     tiled = "void emma::k_tiled<1, float, false, false, false, 4, 4, true>(emma::TileArgs<float>)"
     assert bench._kind(tiled) == ("transport", True)
+    # the split transport as launched now: one plane of prefetch, one LDS buffer
+    one_buf = "void emma::k_tiled<1, float, false, false, false, 4, 1, true, 1>(emma::TileArgs<float>)"
+    assert bench._kind(one_buf) == ("transport", True)
+    assert bench._kind(one_buf.replace("float, false", "float, true", 1)) == ("transport", False)
+    assert bench._kind(one_buf.replace("float", "double"), "fp64") == ("transport", True)
     fused = "void emma::k_tiled<3, float, false, true, true, 4, 0, true>(emma::TileArgs<float>)"
     assert bench._kind(fused) == ("fused_step", True)
     # the HLL tiled transport: <storage, DIAG, tile rows, whole tiles>
